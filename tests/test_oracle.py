@@ -1,0 +1,412 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests re-types an oracle formula and compares it with itself:
+each one checks a limit, a special value, an identity between two different
+computations, a brute-force evaluation, or a literature constant.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (2): special values and limits of the printed closed form
+# ---------------------------------------------------------------------------
+def test_psd_equals_one_at_knee():
+    # At f = f0 the three constant-ish terms sum to 0.16 + 0.52 + 0.32 = 1 and the
+    # seismic wall contributes 4.49^-56 ~ 3e-37.
+    c = _golden("paper_constants.json")
+    assert c["psd_f0_hz"] == O.PSD_F0
+    assert O.psd_initial_ligo(150.0) == pytest.approx(1.0, abs=1e-15)
+
+
+def test_psd_log_slopes_pin_exponents():
+    def slope(f, h=1e-4):
+        return (math.log(O.psd_initial_ligo(f * (1 + h))) - math.log(O.psd_initial_ligo(f * (1 - h)))) / (
+            math.log1p(h) - math.log1p(-h))
+    # Far below the knee the seismic wall (exponent -56) dominates by ~76 decades.
+    assert slope(1.0) == pytest.approx(-56.0, rel=1e-7)
+    # Far above the knee the shot-noise term (exponent +2) dominates.
+    assert slope(1.5e7) == pytest.approx(2.0, abs=1e-8)
+
+
+def test_psd_high_frequency_coefficients():
+    x = 1.0e6
+    S = O.psd_initial_ligo(150.0 * x)
+    assert S / x ** 2 == pytest.approx(0.32, rel=1e-11)
+    x = 1.0e3
+    S = O.psd_initial_ligo(150.0 * x)
+    # S - 0.32 x^2 -> 0.52 (the mid term has decayed as x^-4.52 to ~2e-15).
+    assert S - 0.32 * x * x == pytest.approx(0.52, abs=2e-9)
+
+
+def test_psd_thermal_term_from_knee_value():
+    # Knowing S(f0)=1, the constant 0.52 and the x^2 coefficient 0.32 fixes the
+    # coefficient of the x^-4.52 term at 0.16; check that slope near 100 Hz
+    # matches the mixture implied by those weights (no seismic contribution).
+    f = 100.0
+    x = f / 150.0
+    mid = 0.16 * x ** -4.52
+    hi = 0.32 * x * x
+    expected = (-4.52 * mid + 2.0 * hi) / (mid + 0.52 + hi)
+    h = 1e-5
+    got = (math.log(O.psd_initial_ligo(f * (1 + h))) - math.log(O.psd_initial_ligo(f * (1 - h)))) / (
+        math.log1p(h) - math.log1p(-h))
+    assert got == pytest.approx(expected, rel=1e-6)
+
+
+def test_psd_fp64_accuracy_against_40_digits():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    for f in [30.0, 40.0, 57.3, 150.0, 1024.0, 2047.9]:
+        x = mp.mpf(f) / 150
+        ref = (mp.mpf("4.49") * x) ** -56 + mp.mpf("0.16") * x ** mp.mpf("-4.52") + mp.mpf("0.52") + mp.mpf("0.32") * x ** 2
+        assert abs(O.psd_initial_ligo(f) - float(ref)) <= 8e-15 * float(ref)
+
+
+def test_psd_bins_band_and_inf_outside():
+    n, fs = 1 << 12, 512.0
+    S = O.psd_bins(n, fs, 40.0)
+    k_lo = O.band_lo(n, fs, 40.0)
+    assert k_lo == math.ceil(40.0 * n / fs)
+    assert np.all(np.isinf(S[:k_lo])) and np.isinf(S[n // 2])
+    assert np.all(np.isfinite(S[k_lo: n // 2]))
+
+
+# ---------------------------------------------------------------------------
+# Band edges and constants
+# ---------------------------------------------------------------------------
+def test_tsun_from_nominal_solar_mass_parameter():
+    lit = _golden("literature_values.json")
+    assert O.T_SUN == pytest.approx(lit["gm_sun_nominal_m3_s2"] / lit["speed_of_light_m_s"] ** 3, rel=1e-12)
+
+
+def test_f_isco_textbook_scaling():
+    lit = _golden("literature_values.json")
+    assert O.f_isco(1.0) == pytest.approx(lit["f_isco_hz_times_msun"], abs=lit["f_isco_hz_times_msun_tol"])
+    assert O.f_isco(2.8) * 2.8 == pytest.approx(O.f_isco(1.0), rel=1e-13)
+
+
+def test_band_edges_paper_set_up():
+    c = _golden("paper_constants.json")
+    n = c["segment_points"]
+    fs = c["sample_rate_hz"]
+    assert n / fs == c["segment_seconds"]
+    # 40 Hz x 256 s is an exact bin.
+    mc, eta = synth.mc_eta(1.4, 1.4)
+    k_lo, k_hi = O.band(n, fs, c["f_low_hz"], float(mc), float(eta))
+    assert k_lo == 10240
+    assert k_hi == math.floor(O.f_isco(2.8) * 256.0)
+    assert 401900 < k_hi < 402100
+    # Light templates are cut at Nyquist - 1 bin.
+    mc, eta = synth.mc_eta(1.0, 1.0)
+    assert O.band(n, fs, 40.0, float(mc), float(eta))[1] == n // 2 - 1
+    with pytest.raises(ValueError):
+        O.band(1 << 10, 256.0, 40.0, *map(float, synth.mc_eta(100.0, 100.0)))
+
+
+# ---------------------------------------------------------------------------
+# SPA phase: stationary-phase time/frequency relation and Newtonian limit
+# ---------------------------------------------------------------------------
+def _chirp_time_2pn(f, mc, eta):
+    """Time to coalescence from frequency f at 2PN, typed from the literature
+    (Sathyaprakash & Dhurandhar; Blanchet, Iyer, Will & Wiseman)."""
+    M = mc * eta ** -0.6 * 4.925490947641267e-6
+    v = (math.pi * M * f) ** (1.0 / 3.0)
+    t2 = 743.0 / 252.0 + 11.0 * eta / 3.0
+    t3 = -32.0 * math.pi / 5.0
+    t4 = 3058673.0 / 508032.0 + 5429.0 * eta / 504.0 + 617.0 * eta ** 2 / 72.0
+    return 5.0 * M / (256.0 * eta * v ** 8) * (1.0 + t2 * v ** 2 + t3 * v ** 3 + t4 * v ** 4)
+
+
+@pytest.mark.parametrize("m1,m2", [(1.4, 1.4), (1.0, 3.0), (10.0, 1.2), (17.5, 17.5), (33.0, 1.5)])
+@pytest.mark.parametrize("f", [40.0, 75.0, 200.0])
+def test_spa_phase_derivative_is_minus_chirp_time(m1, m2, f):
+    mc, eta = map(float, synth.mc_eta(m1, m2))
+    h = 1e-20 * f
+    dpsi = float(np.imag(O.spa_phase(f + 1j * h, mc, eta))) / h  # complex-step derivative
+    assert dpsi / (2 * math.pi) == pytest.approx(-_chirp_time_2pn(f, mc, eta), rel=1e-12)
+
+
+def test_spa_tc_shifts_derivative():
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    f, tc = 55.0, 17.25
+    h = 1e-20 * f
+    d0 = float(np.imag(O.spa_phase(f + 1j * h, mc, eta))) / h
+    d1 = float(np.imag(O.spa_phase(f + 1j * h, mc, eta, tc=tc))) / h
+    assert (d1 - d0) / (2 * math.pi) == pytest.approx(tc, rel=1e-12)
+
+
+def test_spa_newtonian_limit_depends_on_chirp_mass_only():
+    lit = _golden("literature_values.json")
+    for (m1, m2) in [(1.4, 1.4), (2.0, 1.0), (30.0, 4.0)]:
+        mc, eta = map(float, synth.mc_eta(m1, m2))
+        f = 1e-7
+        psi = O.spa_phase(f, mc, eta) + math.pi / 4
+        newt = 3.0 / 128.0 * (math.pi * mc * O.T_SUN * f) ** (-5.0 / 3.0)
+        assert psi / newt == pytest.approx(1.0, rel=2e-5)
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    tau0 = 5.0 / 256.0 * (math.pi * 40.0) ** (-8.0 / 3.0) * (mc * O.T_SUN) ** (-5.0 / 3.0)
+    assert tau0 == pytest.approx(lit["newtonian_chirp_time_bns_40hz_s"], abs=lit["newtonian_chirp_time_tol_s"])
+
+
+def test_template_time_domain_ends_at_tc():
+    # The sign convention h = a e^{-i Psi} with Psi containing +2 pi f t_c puts the
+    # chirp before t_c: inverse-transform a template with t_c in the middle.
+    n, fs = 1 << 15, 2048.0
+    T = n / fs
+    mc, eta = map(float, synth.mc_eta(5.0, 5.0))
+    tc = T / 2
+    h = O.spa_template(n, fs, 40.0, mc, eta, tc=tc)
+    ht = np.fft.irfft(h, n)
+    t = np.arange(n) / fs
+    before = np.sum(ht[(t > tc - 4.0) & (t < tc)] ** 2)
+    after = np.sum(ht[(t > tc + 0.05) & (t < tc + 4.05)] ** 2)
+    assert after < 1e-3 * before
+
+
+def test_template_amplitude_and_band():
+    n, fs = 1 << 16, 2048.0
+    mc, eta = map(float, synth.mc_eta(2.0, 2.0))
+    h = O.spa_template(n, fs, 40.0, mc, eta)
+    k_lo, k_hi = O.band(n, fs, 40.0, mc, eta)
+    f = O.freqs(n, fs)
+    assert np.all(h[:k_lo] == 0) and np.all(h[k_hi + 1:] == 0)
+    np.testing.assert_allclose(np.abs(h[k_lo:k_hi + 1]), f[k_lo:k_hi + 1] ** (-7.0 / 6.0), rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Quadrature pair and z = x + i y
+# ---------------------------------------------------------------------------
+def _real_filter(h, stilde, Sn, n, df):
+    """Real matched-filter output of template h: two-sided integral of
+    conj(h) s / S e^{2 pi i f t} over a Hermitian spectrum (via irfft)."""
+    inv = np.where(np.isfinite(Sn), 1.0 / Sn, 0.0)
+    q = 2.0 * df * np.conj(h) * stilde * inv  # weight of each positive-frequency bin
+    q[0] = 0
+    q[n // 2] = 0
+    # irfft(Q) * n = Q_0 + 2 Re sum_{k>0} Q_k e^{+2 pi i jk/N} (for zero DC/Nyquist)
+    return np.fft.irfft(q, n) * n
+
+
+def _noise_segment(n, fs, seed, injection=None):
+    g = O.grid(n, fs)
+    Sn = O.psd_bins(n, fs, 40.0)
+    k_lo = O.band_lo(n, fs, 40.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = synth.coloured_noise(Sn[k_lo: n // 2], g["df"], k_lo, n // 2 + 1, rng, dtype=np.complex128)
+    if injection is not None:
+        mc, eta, snr, j0, phi0 = injection
+        h = O.spa_template(n, fs, 40.0, mc, eta)
+        sig = math.sqrt(O.sigma_sq(h, Sn, g["df"]))
+        s = synth.inject(s, h, snr / sig, phi0, j0, n)
+    return s, Sn, g
+
+
+def test_quadrature_pair_orthogonal():
+    n, fs = 1 << 14, 1024.0
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    g = O.grid(n, fs)
+    Sn = O.psd_bins(n, fs, 40.0)
+    hc = O.spa_template(n, fs, 40.0, mc, eta)
+    hs = O.quadrature_partner(hc)
+    inv = np.where(np.isfinite(Sn), 1.0 / Sn, 0.0)
+    inner = 4 * g["df"] * np.real(np.sum(hc * np.conj(hs) * inv))
+    norm = O.sigma_sq(hc, Sn, g["df"])
+    assert abs(inner) < 1e-14 * norm
+    assert O.sigma_sq(hs, Sn, g["df"]) == pytest.approx(norm, rel=1e-14)
+
+
+def test_phase_offset_half_pi_gives_quadrature_partner():
+    # Sec. 1.1: the alpha = 0 and alpha = pi/2 templates are h_c and h_s with
+    # h_c = -i h_s, i.e. the pi/2-offset template is i h_c.
+    n, fs = 1 << 13, 1024.0
+    mc, eta = map(float, synth.mc_eta(1.2, 2.2))
+    hc = O.spa_template(n, fs, 40.0, mc, eta, phic=0.0)
+    hs = O.spa_template(n, fs, 40.0, mc, eta, phic=math.pi / 2)
+    np.testing.assert_allclose(hc, -1j * hs, atol=1e-15 * np.max(np.abs(hc)))
+
+
+def test_z_is_x_plus_iy_from_two_real_filters():
+    n, fs = 1 << 14, 1024.0
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    s, Sn, g = _noise_segment(n, fs, 11, injection=(mc, eta, 12.0, 1234, 0.7))
+    hc = O.spa_template(n, fs, 40.0, mc, eta)
+    hs = O.quadrature_partner(hc)
+    z = O.filter_z(s, Sn, hc, n, g["df"])
+    x = _real_filter(hc, s, Sn, n, g["df"])
+    y = _real_filter(hs, s, Sn, n, g["df"])
+    scale = np.max(np.abs(z))
+    np.testing.assert_allclose(z.real, x, atol=1e-12 * scale)
+    np.testing.assert_allclose(z.imag, y, atol=1e-12 * scale)
+    # The printed conjugate placement is the time reversal of the same series.
+    zl = O.filter_z_literal(s, Sn, hc, n, g["df"])
+    rev = (-np.arange(n)) % n
+    np.testing.assert_allclose(zl, np.conj(z[rev]), atol=1e-12 * scale)
+
+
+# ---------------------------------------------------------------------------
+# FFT convention: brute force, Parseval, impulse
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [8, 64, 512])
+def test_inverse_dft_matches_naive(n):
+    rng = np.random.default_rng(n)
+    q = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    got = O.inverse_dft(q)
+    ref = O.naive_dft(q, +1)
+    # naive DFT brute force: explicit double loop for the smallest size
+    if n == 8:
+        brute = np.array([sum(q[k] * complex(math.cos(2 * math.pi * j * k / n), math.sin(2 * math.pi * j * k / n))
+                              for k in range(n)) for j in range(n)])
+        np.testing.assert_allclose(ref, brute, atol=1e-12)
+    np.testing.assert_allclose(got, ref, atol=1e-12 * n)
+
+
+def test_parseval_and_impulse():
+    n = 1 << 12
+    rng = np.random.default_rng(3)
+    q = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    z = O.inverse_dft(q)
+    assert np.sum(np.abs(z) ** 2) == pytest.approx(n * np.sum(np.abs(q) ** 2), rel=1e-12)
+    k0 = 37
+    d = np.zeros(n, complex)
+    d[k0] = 1.0
+    j = np.arange(n)
+    np.testing.assert_allclose(O.inverse_dft(d), np.exp(2j * np.pi * j * k0 / n), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (4): Riemann sum against adaptive quadrature of the continuous integral
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,fs,m", [(1 << 16, 2048.0, 1.4), (1 << 20, 4096.0, 1.4), (1 << 20, 4096.0, 10.0)])
+def test_sigma_against_quadrature(n, fs, m):
+    integrate = pytest.importorskip("scipy.integrate")
+    mc, eta = map(float, synth.mc_eta(m, m))
+    g = O.grid(n, fs)
+    Sn = O.psd_bins(n, fs, 40.0)
+    h = O.spa_template(n, fs, 40.0, mc, eta)
+    k_lo, k_hi = O.band(n, fs, 40.0, mc, eta)
+    s2 = O.sigma_sq(h, Sn, g["df"])
+
+    def integrand(f):
+        return 4.0 * f ** (-7.0 / 3.0) / O.psd_initial_ligo(f)
+    f_lo, f_hi = k_lo * g["df"], k_hi * g["df"]
+    val, _ = integrate.quad(integrand, f_lo, f_hi, limit=400, epsabs=0, epsrel=1e-13)
+    # Trapezoid end corrections turn the bin sum into an O(df^2) estimate.
+    trap = s2 - 0.5 * g["df"] * (integrand(f_lo) + integrand(f_hi))
+    assert trap == pytest.approx(val, rel=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (1)-(3) end to end: noiseless injection, Cauchy-Schwarz, noise statistics
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("j0,phi0", [(0, 0.0), (4321, 1.1), (65535, 5.9)])
+def test_noiseless_injection_recovers_snr(j0, phi0):
+    n, fs = 1 << 16, 2048.0
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    g = O.grid(n, fs)
+    Sn = O.psd_bins(n, fs, 40.0)
+    h = O.spa_template(n, fs, 40.0, mc, eta)
+    sig = math.sqrt(O.sigma_sq(h, Sn, g["df"]))
+    s = synth.inject(np.zeros(n // 2 + 1, complex), h, 10.0 / sig, phi0, j0, n)
+    out = O.filter_unit(n, fs, 40.0, mc, eta, s, Sn, threshold=9.99, return_series=True)
+    assert out["j"] == j0
+    assert out["rho"] == pytest.approx(10.0, rel=1e-12)
+    assert np.all(out["series"] <= 10.0 * (1 + 1e-12))
+    assert out["n_above"] >= 1
+    zl = O.filter_z_literal(s, Sn, h, n, g["df"])
+    assert int(np.argmax(np.abs(zl))) == (n - j0) % n
+
+
+def test_noise_only_rho_squared_mean_is_two():
+    n, fs = 1 << 14, 1024.0
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    vals = []
+    for seed in range(12):
+        s, Sn, g = _noise_segment(n, fs, 1000 + seed)
+        out = O.filter_unit(n, fs, 40.0, mc, eta, s, Sn, return_series=True)
+        vals.append(np.mean(out["series"] ** 2))
+    assert np.mean(vals) == pytest.approx(2.0, rel=0.03)
+
+
+def test_peak_tie_break_and_window():
+    rho = np.array([0.0, 3.0, 1.0, 3.0, 2.0, 3.0])
+    assert O.peak(rho) == (3.0, 1, 0)
+    assert O.peak(rho, threshold=2.0) == (3.0, 1, 4)
+    assert O.peak(rho, j_begin=2, j_end=5) == (3.0, 3, 0)
+
+
+def test_bank_mirror_pairs_identical():
+    n, fs = 1 << 14, 1024.0
+    s, Sn, g = _noise_segment(n, fs, 5)
+    a = synth.mc_eta(1.0, 3.0)
+    b = synth.mc_eta(3.0, 1.0)
+    assert a[0] == b[0] and a[1] == b[1]
+    oa = O.filter_unit(n, fs, 40.0, float(a[0]), float(a[1]), s, Sn)
+    ob = O.filter_unit(n, fs, 40.0, float(b[0]), float(b[1]), s, Sn)
+    assert oa == ob
+
+
+# ---------------------------------------------------------------------------
+# Gradient of rho^2
+# ---------------------------------------------------------------------------
+def _grad_case(noise=True):
+    n, fs = 1 << 14, 1024.0
+    mc, eta = map(float, synth.mc_eta(1.6, 1.3))
+    j0 = 5000
+    if noise:
+        s, Sn, g = _noise_segment(n, fs, 21, injection=(mc, eta, 15.0, j0, 0.4))
+    else:
+        g = O.grid(n, fs)
+        Sn = O.psd_bins(n, fs, 40.0)
+        h = O.spa_template(n, fs, 40.0, mc, eta)
+        sig = math.sqrt(O.sigma_sq(h, Sn, g["df"]))
+        s = synth.inject(np.zeros(n // 2 + 1, complex), h, 15.0 / sig, 0.4, j0, n)
+    k_lo, k_hi = O.band(n, fs, 40.0, mc, eta)
+    return n, fs, mc, eta, j0 * g["dt"], s, Sn, k_lo, k_hi
+
+
+def test_gradient_matches_finite_differences():
+    n, fs, mc, eta, t0, s, Sn, k_lo, k_hi = _grad_case()
+    theta = (mc * 1.0003, eta * 0.999, t0 + 2e-4)
+    F, Z, grad = O.snr_sq(theta, s, Sn, n, fs, k_lo, k_hi, with_grad=True)
+    fd = O.snr_sq_fd_grad(theta, s, Sn, n, fs, k_lo, k_hi)
+    D = np.array([theta[0] * 1e-3, 1e-3, 1e-4])
+    assert np.linalg.norm(D * (grad - fd)) <= 1e-5 * np.linalg.norm(D * fd) + 1e-9 * F
+    np.testing.assert_allclose(grad, fd, rtol=1e-4)
+
+
+def test_gradient_vanishes_at_noiseless_injection():
+    n, fs, mc, eta, t0, s, Sn, k_lo, k_hi = _grad_case(noise=False)
+    F, Z, grad = O.snr_sq((mc, eta, t0), s, Sn, n, fs, k_lo, k_hi, with_grad=True)
+    assert F == pytest.approx(225.0, rel=1e-12)
+    D = np.array([mc * 1e-3, 1e-3, 1e-4])
+    assert np.linalg.norm(D * grad) < 1e-8 * F
+    # A displaced point has a clearly non-zero gradient that points back.
+    F2, _, g2 = O.snr_sq((mc, eta, t0 + 3e-4), s, Sn, n, fs, k_lo, k_hi, with_grad=True)
+    assert F2 < F and g2[2] < 0
+
+
+def test_snr_sq_equals_filter_output_at_sample_time():
+    n, fs, mc, eta, t0, s, Sn, k_lo, k_hi = _grad_case()
+    g = O.grid(n, fs)
+    h = O.spa_template(n, fs, 40.0, mc, eta)
+    z = O.filter_z(s, Sn, h, n, g["df"])
+    sig2 = O.sigma_sq(h, Sn, g["df"])
+    j = 4097
+    F, Z, _ = O.snr_sq((mc, eta, j * g["dt"]), s, Sn, n, fs, k_lo, k_hi)
+    assert Z == pytest.approx(complex(z[j]), rel=1e-10)
+    assert F == pytest.approx(abs(z[j]) ** 2 / sig2, rel=1e-10)
