@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Throughput of the matched-filter hot path on one MI355X.
+
+One step = one mf_filter call over the whole workload: per-segment data
+weights, then for every (template, segment) unit the stationary-phase template,
+the weighted product, the 2^20-point inverse DFT, rho = |z|/sigma and its
+peak / threshold count.  Inputs (data spectra, PSD, bank) are resident in HBM
+before the timed region.
+
+Prints ONE JSON line: units/s (templates x segments per second), the roofline
+of the dominant kernel (HIP events on the launch stream during the timed
+steps), the plain FP64 path on the same GPU, and the FP64 oracle timed on the
+host cores over a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2|3|5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "templates×segments/s at 2^20-pt IFFT; HBM GB/s fraction; vs FP64 path"
+UNIT = "templates×segments/s"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f) for f in ("k_filter.hip", "mf_device.hpp")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload_bank(cfg: int):
+    """(mc, eta) of the workload's template bank."""
+    if cfg == 2:
+        return synth.bank_mc_eta_grid()
+    if cfg == 3:
+        mc, eta, _, _ = synth.bank_uneven(8192, synth.rngs(3, 1)[0])
+        return mc, eta
+    if cfg == 5:
+        mc, eta, _, _ = synth.bank_uneven(32768, synth.rngs(5, 1)[0])
+        return mc, eta
+    raise SystemExit(f"workload {cfg} is not a filter-throughput workload (use 2, 3 or 5)")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores (runs before any GPU use)
+# ---------------------------------------------------------------------------
+_CPU = {}
+
+
+def _cpu_unit(t: int):
+    import oracle as O
+    d = _CPU
+    out = O.filter_unit(d["n"], d["fs"], 40.0, float(d["mc"][t]), float(d["eta"][t]), d["s"], d["Sn"])
+    return out["rho"]
+
+
+def cpu_baseline(cfg: int, seconds: float, max_procs: int):
+    import multiprocessing as mp
+
+    import oracle as O
+    wl = synth.WORKLOADS[cfg]
+    n, fs = wl.n, wl.fs
+    g = O.grid(n, fs)
+    Sn = O.psd_bins(n, fs, wl.f_low)
+    k_lo = O.band_lo(n, fs, wl.f_low)
+    rng = synth.rngs(cfg, 1)[0]
+    s = synth.coloured_noise(Sn[k_lo: n // 2], g["df"], k_lo, n // 2 + 1, rng, dtype=np.complex64)
+    mc, eta = workload_bank(cfg)
+    _CPU.update(n=n, fs=fs, s=s.astype(np.complex128), Sn=Sn, mc=mc, eta=eta)
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    _cpu_unit(0)
+    t_one = time.perf_counter() - t0
+    n_units = int(min(len(mc), max(procs, round(procs * seconds / max(t_one, 1e-3)))))
+    idx = np.linspace(0, len(mc) - 1, n_units).astype(int).tolist()
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        pool.map(_cpu_unit, idx, chunksize=1)
+    dt = time.perf_counter() - t0
+    return {"value": n_units / dt, "unit": UNIT, "cores": procs, "kind": "oracle",
+            "sample": f"{n_units} of the {len(mc)} templates x 1 segment (N={n}), FP64 NumPy oracle, "
+                      f"{procs} single-threaded processes, {dt:.1f} s wall"}
+
+
+# ---------------------------------------------------------------------------
+# GPU
+# ---------------------------------------------------------------------------
+def read_traffic(kernel: str, workload: str, khash: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it is
+    for the current kernel source; else None."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != khash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(args):
+    import torch
+
+    import paper_0906_4175_amd as mf
+    from paper_0906_4175_amd import _lib as L
+
+    cfg = args.workload
+    wl = synth.WORKLOADS[cfg]
+    dev = torch.device("cuda:0")
+    grid = mf.Grid(wl.n, wl.fs, wl.f_low)
+    Sn = mf.psd(grid, device=dev)
+    Sn_h = Sn.cpu().numpy()
+    mc, eta = workload_bank(cfg)
+    n_seg = wl.n_seg
+    k_lo = grid.k_lo
+    rngs = synth.rngs(cfg, n_seg + 1)
+    segs = []
+    for sidx in range(n_seg):
+        segs.append(synth.coloured_noise(Sn_h[k_lo: wl.n // 2], grid.df, k_lo, wl.n // 2 + 1, rngs[sidx],
+                                         dtype=np.complex64))
+    if cfg == 2:
+        # five injections with SNR 8-15, templates synthesised by the library itself
+        injs = synth.injection_params(rngs[-1], 5, wl.n)
+        imc, ieta = synth.mc_eta([i["m1"] for i in injs], [i["m2"] for i in injs])
+        ib = mf.spa_bank(grid, imc, ieta, Sn, "fp32_ph64", materialise=True)
+        ht = ib.htilde.cpu().numpy()
+        for q, inj in enumerate(injs):
+            segs[0] = synth.inject(segs[0], ht[q], inj["snr"] / ib.sigma[q], inj["phi0"], inj["j0"], wl.n)
+    S32 = torch.from_numpy(np.stack(segs)).to(dev)
+    S64 = S32.to(torch.complex128)
+
+    def measure(prec: str, steps: int, warmup: int, stride: int):
+        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        st = S64 if prec == "fp64" else S32
+        ws = torch.empty(mf.filter_workspace_bytes(grid, prec, bank.n_tmpl, n_seg), dtype=torch.uint8, device=dev)
+        peaks = torch.empty(2 * bank.n_tmpl * n_seg, dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            res = mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
+        torch.cuda.synchronize()
+        lib = L.load()
+        lib.mf_timing_enable(stride)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        import ctypes as C
+        p1, p2 = C.c_double(), C.c_double()
+        n1, n2, u1, u2 = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(lib.mf_timing_read(C.byref(p1), C.byref(n1), C.byref(u1), C.byref(p2), C.byref(n2), C.byref(u2)))
+        lib.mf_timing_enable(0)
+        b = 16 if prec == "fp64" else 8
+        n_act = (bank.k_hi.astype(np.int64) - k_lo + 1)
+        # per-unit algorithmic bytes, averaged over the units of the workload
+        pass1_unit = float(np.mean(b * n_act + b * wl.n))
+        pass2_unit = float(b * wl.n + 16)
+        out = {"prec": prec, "ms_per_step": 1e3 * wall / steps, "steps": steps,
+               "units": bank.n_tmpl * n_seg, "peaks": res,
+               "pass1": {"ms": p1.value, "launches": n1.value, "units": u1.value, "bytes_per_unit": pass1_unit},
+               "pass2": {"ms": p2.value, "launches": n2.value, "units": u2.value, "bytes_per_unit": pass2_unit},
+               "b_alg_unit": float(np.mean(b * n_act + 2 * b * wl.n + 16))}
+        return out
+
+    main = measure(args.precision, args.steps, args.warmup, args.timing_stride)
+    fp64 = None
+    if args.fp64_steps > 0:
+        fp64 = measure("fp64", args.fp64_steps, 1, args.timing_stride)
+    return main, fp64
+
+
+def roofline(m, workload_name: str, khash: str):
+    best = None
+    for name in ("pass1", "pass2"):
+        p = m[name]
+        if p["launches"] == 0 or p["ms"] <= 0:
+            continue
+        avg_ms = p["ms"] / p["launches"]
+        bytes_per_launch = p["bytes_per_unit"] * p["units"] / p["launches"]
+        ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        rec = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+               "kernel": f"k_{name}_{m['prec']}", "avg_launch_ms": round(avg_ms, 5),
+               "alg_bytes_per_launch": round(bytes_per_launch), "share_of_kernel_time": None}
+        tb = read_traffic(f"{name}_{m['prec']}", workload_name, khash)
+        if tb is not None:
+            rec["traffic"] = round(tb)
+        rec["_total_ms"] = p["ms"]
+        if best is None or p["ms"] > best["_total_ms"]:
+            best = rec
+    tot = m["pass1"]["ms"] + m["pass2"]["ms"]
+    if best is not None:
+        best["share_of_kernel_time"] = round(best["_total_ms"] / tot, 3) if tot > 0 else None
+        del best["_total_ms"]
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--precision", default="fp32_ph64", choices=["fp32_ph64", "fp32", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--timing-stride", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-procs", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "the per-GPU share of a sharded bank is the single-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+    wl = synth.WORKLOADS[args.workload]
+
+    cpu = None
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        print(f"[bench] cpu baseline: oracle on host cores (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.workload, args.cpu_seconds, args.cpu_procs)
+        print(f"[bench] cpu baseline {cpu['value']:.2f} {UNIT} on {cpu['cores']} cores", file=sys.stderr, flush=True)
+
+    print(f"[bench] gpu workload {wl.name} precision {args.precision}", file=sys.stderr, flush=True)
+    m, fp64 = run_gpu(args)
+    khash = kernel_hash()
+    value = m["units"] / (m["ms_per_step"] * 1e-3)
+    eff_gbs = m["b_alg_unit"] * m["units"] / (m["ms_per_step"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(m["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision != "fp64" else "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "fs": wl.fs, "f_low": wl.f_low,
+                   "n_tmpl": m["units"] // wl.n_seg, "n_seg": wl.n_seg, "precision": args.precision,
+                   "phase_dtype": "f64" if args.precision != "fp32" else "f32", "sigma_dtype": "f64"},
+        "effective_hbm": {"achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(eff_gbs / HBM_PEAK_GBS, 4),
+                          "b_alg_per_unit": round(m["b_alg_unit"])},
+        "roofline": roofline(m, wl.name, khash),
+        "cpu_baseline": cpu,
+        "kernel_source_hash": khash,
+    }
+    if fp64 is not None:
+        v64 = fp64["units"] / (fp64["ms_per_step"] * 1e-3)
+        e64 = fp64["b_alg_unit"] * fp64["units"] / (fp64["ms_per_step"] * 1e-3) / 1e9
+        line["fp64_path"] = {"value": round(v64, 1), "ms_per_step": round(fp64["ms_per_step"], 4),
+                             "steps": fp64["steps"], "effective_hbm_frac": round(e64 / HBM_PEAK_GBS, 4),
+                             "roofline": roofline(fp64, wl.name, khash),
+                             "speedup_fp32_over_fp64": round(value / v64, 3)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

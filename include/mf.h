@@ -1,0 +1,226 @@
+/*
+ * mf.h -- C ABI of libmf, an MI355X (gfx950) matched filter for compact-binary
+ * inspiral searches.
+ *
+ * What it computes (arXiv:0906.4175, Sec. 1.1):
+ *   Eq. (2)  S_n(f) = (4.49 f/f0)^-56 + 0.16 (f/f0)^-4.52 + 0.52 + 0.32 (f/f0)^2
+ *   Eq. (1)  z(t)   = 4 int_0^inf conj(h_c(f)) s(f) / S_n(f) e^{2 pi i f t} df
+ *            (conjugate on the template: the reading that makes z = x + i y
+ *             with x, y the responses of h_c and h_s, h_c = -i h_s)
+ *   Eq. (4)  sigma^2 = 4 int |h_c(f)|^2 / S_n(f) df
+ *   Eq. (3)  rho(t) = |z(t)| / sigma, then its peak over t and a threshold count
+ * with h_c the 2PN stationary-phase template with Newtonian amplitude that the
+ * paper uses (Sec. 1.1), cut at f_low and at min(f_ISCO, Nyquist).
+ *
+ * Discretisation: N-point segments at sample rate fs, T = N/fs, df = 1/T,
+ * one-sided bins k = 0..N/2 at f_k = k df; int df -> df * sum_k; the time
+ * series is the unnormalised inverse DFT sum_k q_k e^{+2 pi i jk/N}.  The band
+ * is k_lo = ceil(f_low T) .. k_hi = min(floor(f_ISCO T), N/2 - 1);
+ * f_ISCO = 1/(6^{3/2} pi M), M = (m1+m2) G M_sun/c^3, G M_sun/c^3 =
+ * 4.925490947641267e-6 s.  S_n carries no overall scale (S_0 = 1).
+ *
+ * Conventions for every call:
+ *  - Pointers named *_dev are device pointers; *_host are host pointers.
+ *    The caller owns every buffer.  The library allocates no device memory.
+ *  - Complex arrays are interleaved (re, im) pairs: complex64 = 2 x float,
+ *    complex128 = 2 x double.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Hot calls only
+ *    enqueue work; setup calls may synchronise the stream.
+ *  - Every call validates its arguments before enqueueing anything and returns
+ *    an mf_status; on error nothing is enqueued and mf_last_error() holds a
+ *    message (thread-local).  A HIP error of earlier asynchronous work can
+ *    surface as MF_E_HIP on a later call.  Outputs are undefined after an
+ *    error.  NaN/Inf inputs propagate to the affected outputs.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same type as hipStream_t. */
+typedef struct ihipStream_t* mf_stream_t;
+
+typedef enum {
+    MF_OK = 0,
+    MF_E_ARG = -1,         /* null pointer, bad enum, bad count            */
+    MF_E_SHAPE = -2,       /* N not a power of two in range, bad window     */
+    MF_E_BAND = -3,        /* empty band (k_hi < k_lo) or f_low out of range */
+    MF_E_HIP = -4,         /* HIP runtime error                             */
+    MF_E_WORKSPACE = -5,   /* workspace too small                           */
+    MF_E_UNSUPPORTED = -6  /* valid request this build does not implement   */
+} mf_status;
+
+typedef enum {
+    MF_FP64 = 0,       /* plain path: data, phase, products, FFT, sigma in FP64   */
+    MF_FP32_PH64 = 1,  /* FP32 data/products/FFT; SPA phase and sigma in FP64     */
+    MF_FP32 = 2        /* FP32 throughout except sigma (precision study only)      */
+} mf_precision;
+
+typedef enum {
+    MF_SIGMA_FP64 = 0,    /* sigma^2 accumulated in FP64                 */
+    MF_SIGMA_COMP32 = 1   /* compensated (Kahan) FP32 accumulation        */
+} mf_sigma_mode;
+
+/* Segment grid: N = 2^m with 2^10 <= N <= 2^22, sample rate fs [Hz], low
+ * frequency cutoff f_low [Hz] with 0 < f_low < fs/2, PSD knee f0 [Hz]
+ * (150 for Eq. (2)). */
+typedef struct {
+    int64_t n;
+    double fs;
+    double f_low;
+    double f0;
+} mf_grid;
+
+/* Per (template, segment) result.  rho is the maximum of |z_j|/sigma over the
+ * search window, j its lowest index, n_above the number of window samples
+ * with rho_j >= the threshold.  In the FP32 modes rho is computed from the
+ * FP32 |z|^2 and the FP64 sigma. */
+typedef struct {
+    double rho;
+    int32_t j;
+    int32_t n_above;
+} mf_peak;
+
+/* Options of mf_filter.  A NULL options pointer means: no threshold count
+ * (rho_threshold = +inf), window = the whole segment, no series. */
+typedef struct {
+    double rho_threshold;              /* count rho_j >= this (+inf: count none)        */
+    int64_t j_begin, j_end;            /* search window [j_begin, j_end); j_end=0: N   */
+    const int32_t* series_units_dev;   /* nullable: unit ids u = t*n_seg + s to store   */
+    int32_t n_series;                  /* number of ids (rho_dev holds n_series x N)    */
+} mf_filter_opts;
+
+/* One template of a device bank (64 bytes, opaque to callers but fixed). */
+typedef struct {
+    double b1, b2, b3, b5;  /* SPA phase in cycles: sum_n b_n u^n, u = k^(-1/3)  */
+    double c0;              /* constant phase in cycles                          */
+    double sigma;           /* sqrt of Eq. (4) over the template's band          */
+    int32_t k_lo, k_hi;     /* band                                              */
+    float inv_sigma;        /* 1/sigma rounded to float                          */
+    int32_t reserved;
+} mf_bank_entry;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* mf_last_error(void);
+
+/* Library version string. */
+const char* mf_version(void);
+
+/* Bytes of a device bank of n_tmpl templates (n_tmpl * sizeof(mf_bank_entry)). */
+size_t mf_bank_bytes(int64_t n_tmpl);
+
+/* Bytes of device workspace mf_filter needs for this request (0 on invalid
+ * arguments, with mf_last_error set). */
+size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
+                                 int64_t n_tmpl, int64_t n_seg);
+
+/*
+ * mf_psd -- Eq. (2) on the one-sided bins (setup call).
+ *   Sn_dev     [N/2+1] double, written: S_n(k df) for k_lo <= k <= N/2-1,
+ *              +inf at the other bins (DC, below f_low, Nyquist), so that
+ *              1/S_n = 0 there.
+ *   prefix_dev nullable [N/2+1] double: P_k = sum_{k'<=k} f_k'^(-7/3) / S_n,k'
+ *              (FP64 running sum; 4 df (P_khi - P_{klo-1}) is sigma^2).
+ * Errors: MF_E_ARG (null grid/Sn_dev), MF_E_SHAPE (N), MF_E_BAND (f_low).
+ */
+mf_status mf_psd(const mf_grid* grid, double* Sn_dev, double* prefix_dev,
+                 mf_stream_t stream);
+
+/*
+ * mf_spa_bank -- 2PN stationary-phase templates (Sec. 1.1) and their norm
+ * sigma (Eq. (4)) (setup call; synchronises `stream`).
+ *   mc_host, eta_host [n_tmpl]: chirp mass [M_sun] > 0 and 0 < eta <= 1/4.
+ *   Sn_dev     [N/2+1] double from mf_psd.
+ *   prec       selects the materialised template's type (complex128 for
+ *              MF_FP64, complex64 otherwise); the bank itself is FP64.
+ *   sigma_mode FP64 or compensated-FP32 accumulation of sigma^2.
+ *   bank_dev   mf_bank_bytes(n_tmpl) bytes, written.
+ *   khi_host   nullable [n_tmpl] int32, written with k_hi.
+ *   sigma_host nullable [n_tmpl] double, written with sigma.
+ *   htilde_dev nullable [n_tmpl][N/2+1] complex: h_c(f_k) = f_k^(-7/6)
+ *              exp(-i Psi(f_k)) in band, 0 outside (t_c = phi_c = 0).
+ * Errors: MF_E_ARG (null pointers, mc <= 0, eta outside (0, 1/4]),
+ *         MF_E_SHAPE, MF_E_BAND (a template whose band is empty; the message
+ *         names its index), MF_E_HIP.
+ */
+mf_status mf_spa_bank(const mf_grid* grid, const double* mc_host, const double* eta_host,
+                      int64_t n_tmpl, const double* Sn_dev, mf_precision prec,
+                      mf_sigma_mode sigma_mode, void* bank_dev, int32_t* khi_host,
+                      double* sigma_host, void* htilde_dev, mf_stream_t stream);
+
+/*
+ * mf_filter -- Eq. (1), (3) and the peak search for every (template, segment)
+ * unit (hot call: asynchronous, no allocation, no synchronisation).
+ *   bank_dev    from mf_spa_bank (same grid and Sn).
+ *   stilde_dev  [n_seg][N/2+1] complex one-sided data spectra (complex128 for
+ *               MF_FP64, complex64 otherwise), s_k = dt sum_j s_j e^{-2 pi i jk/N}.
+ *   Sn_dev      [N/2+1] double from mf_psd.
+ *   workspace   >= mf_filter_workspace_bytes(grid, prec, n_tmpl, n_seg) bytes,
+ *               256-byte aligned.
+ *   peaks_dev   [n_tmpl][n_seg] mf_peak, written.
+ *   rho_dev     nullable; with opts->n_series > 0 it receives rho_j for the
+ *               listed units, [n_series][N], float (FP32 modes) or double
+ *               (MF_FP64).
+ * Errors: MF_E_ARG, MF_E_SHAPE (bad window), MF_E_WORKSPACE, MF_E_HIP.
+ */
+mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
+                    const void* stilde_dev, int64_t n_seg, const double* Sn_dev,
+                    mf_precision prec, const mf_filter_opts* opts,
+                    void* workspace_dev, size_t workspace_bytes,
+                    mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream);
+
+/*
+ * mf_ifft -- the unnormalised complex inverse DFT z_j = sum_k q_k e^{+2 pi i jk/N}
+ * of `batch` contiguous N-point arrays, with the same two-pass kernels the
+ * filter uses (diagnostic / test entry point).  q_dev and z_dev are
+ * [batch][N] complex64 (MF_FP32*) or complex128 (MF_FP64) and may not
+ * overlap.  workspace as for mf_ifft_workspace_bytes.
+ */
+size_t mf_ifft_workspace_bytes(int64_t n, mf_precision prec, int64_t batch);
+mf_status mf_ifft(int64_t n, mf_precision prec, const void* q_dev, void* z_dev,
+                  int64_t batch, void* workspace_dev, size_t workspace_bytes,
+                  mf_stream_t stream);
+
+/*
+ * mf_snr_grad -- F = rho^2 = |Z|^2 / sigma^2 at continuous parameters and,
+ * optionally, its gradient (hot call).
+ *   theta_dev [n][3] double: chirp mass [M_sun], eta, t_c [s] per trigger.
+ *   khi_dev   nullable [n] int32: frozen upper band edge per trigger (else
+ *             computed from theta); the lower edge is k_lo of the grid.
+ *   seg_dev   [n] int32 segment index of each trigger (0 <= seg < n_seg).
+ *   Z = 4 df sum_{k in band} f_k^(-7/6) e^{+i Psi_k(theta)} s_k / S_k, i.e. z(t)
+ *   of Eq. (1) at the continuous time t = t_c; sigma as in Eq. (4) over the
+ *   same band.
+ *   Z_dev     [n] complex128, written (kept for the backward pass).
+ *   rho2_dev  [n] double, written with F.
+ *   gbar_dev  nullable [n] double: if given, grad_dev [n][3] double receives
+ *             gbar * dF/dtheta.
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_BAND, MF_E_HIP.
+ */
+mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_t* khi_dev,
+                      const int32_t* seg_dev, int64_t n, const void* stilde_dev, int64_t n_seg,
+                      const double* Sn_dev, mf_precision prec, double* Z_dev, double* rho2_dev,
+                      const double* gbar_dev, double* grad_dev, mf_stream_t stream);
+
+/*
+ * Measurement hook (not part of the method).  With stride > 0, mf_filter
+ * records a HIP event pair on its stream around the pass-1 and pass-2
+ * launches of every stride-th batch; mf_timing_read waits for the recorded
+ * events, returns the summed kernel durations [ms], launch counts and summed
+ * (template, segment) units of the sampled launches, and clears the record.
+ * stride = 0 disables recording.  Host state only; not thread-safe.
+ */
+mf_status mf_timing_enable(int32_t stride);
+mf_status mf_timing_read(double* pass1_ms, int64_t* pass1_launches, int64_t* pass1_units,
+                         double* pass2_ms, int64_t* pass2_launches, int64_t* pass2_units);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

@@ -1,0 +1,244 @@
+"""MI355X (gfx950) matched filter for compact-binary inspiral searches.
+
+Python binding of libmf (include/mf.h): argument marshalling only.  Every
+step of the path runs in the HIP kernels of libmf.so; PyTorch provides device
+memory and the current stream.  There is no CPU fallback: importing the
+package without the built library raises.
+
+Calls follow arXiv:0906.4175, Sec. 1.1: :func:`psd` is Eq. (2), :func:`spa_bank`
+builds the 2PN stationary-phase templates and their norm (Eq. (4)),
+:func:`filter` evaluates Eq. (1) and Eq. (3) with the peak / threshold search,
+:func:`snr_sq` and :class:`SnrSq` give rho^2 at continuous template parameters
+and its gradient.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
+           "PRECISIONS", "version"]
+
+PRECISIONS = {"fp64": L.MF_FP64, "fp32_ph64": L.MF_FP32_PH64, "fp32": L.MF_FP32}
+SIGMA_MODES = {"fp64": L.MF_SIGMA_FP64, "comp32": L.MF_SIGMA_COMP32}
+
+_clib = L.load()
+
+
+def version() -> str:
+    return _clib.mf_version().decode()
+
+
+@dataclass(frozen=True)
+class Grid:
+    """N-point segment at sample rate fs [Hz], low cutoff f_low [Hz], PSD knee f0 [Hz]."""
+    n: int
+    fs: float
+    f_low: float = 40.0
+    f0: float = 150.0
+
+    def c(self) -> L.MfGrid:
+        return L.MfGrid(int(self.n), float(self.fs), float(self.f_low), float(self.f0))
+
+    @property
+    def T(self) -> float:
+        return self.n / self.fs
+
+    @property
+    def df(self) -> float:
+        return self.fs / self.n
+
+    @property
+    def k_lo(self) -> int:
+        return int(math.ceil(self.f_low * (self.n / self.fs)))
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _cdtype(prec: int) -> torch.dtype:
+    return torch.complex128 if prec == L.MF_FP64 else torch.complex64
+
+
+def _stream(device: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _require_cuda(*tensors):
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libmf operates on GPU tensors only")
+
+
+def psd(grid: Grid, prefix: bool = False, device="cuda"):
+    """S_n on the one-sided bins (Eq. (2)), +inf outside [k_lo, N/2-1]; optionally P_k."""
+    dev = torch.device(device)
+    Sn = torch.empty(grid.n // 2 + 1, dtype=torch.float64, device=dev)
+    P = torch.empty_like(Sn) if prefix else None
+    g = grid.c()
+    L.check(_clib.mf_psd(C.byref(g), _ptr(Sn), _ptr(P), _stream(dev)))
+    return (Sn, P) if prefix else Sn
+
+
+@dataclass
+class Bank:
+    grid: Grid
+    data: torch.Tensor          # device bytes (mf_bank_entry[n_tmpl])
+    n_tmpl: int
+    k_hi: np.ndarray
+    sigma: np.ndarray
+    htilde: torch.Tensor | None = None
+
+
+def spa_bank(grid: Grid, mc, eta, Sn: torch.Tensor, precision="fp32_ph64", sigma_mode="fp64",
+             materialise: bool = False) -> Bank:
+    """2PN stationary-phase bank for chirp masses mc [M_sun] and symmetric mass ratios eta."""
+    _require_cuda(Sn)
+    mc = np.ascontiguousarray(mc, dtype=np.float64).ravel()
+    eta = np.ascontiguousarray(eta, dtype=np.float64).ravel()
+    if mc.shape != eta.shape:
+        raise ValueError("mc and eta must have the same length")
+    n_tmpl = int(mc.shape[0])
+    prec = _prec(precision)
+    nbytes = int(_clib.mf_bank_bytes(n_tmpl))
+    data = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=Sn.device)
+    khi = np.zeros(n_tmpl, dtype=np.int32)
+    sig = np.zeros(n_tmpl, dtype=np.float64)
+    ht = None
+    if materialise:
+        ht = torch.empty((n_tmpl, grid.n // 2 + 1), dtype=_cdtype(prec), device=Sn.device)
+    g = grid.c()
+    DP = C.POINTER(C.c_double)
+    st = _clib.mf_spa_bank(C.byref(g), mc.ctypes.data_as(DP), eta.ctypes.data_as(DP), n_tmpl, _ptr(Sn), prec,
+                          SIGMA_MODES[sigma_mode] if isinstance(sigma_mode, str) else int(sigma_mode),
+                          _ptr(data), khi.ctypes.data_as(C.POINTER(C.c_int32)), sig.ctypes.data_as(DP), _ptr(ht),
+                          _stream(Sn.device))
+    L.check(st)
+    return Bank(grid, data, n_tmpl, khi, sig, ht)
+
+
+def filter_workspace_bytes(grid: Grid, precision, n_tmpl: int, n_seg: int) -> int:
+    g = grid.c()
+    nb = int(_clib.mf_filter_workspace_bytes(C.byref(g), _prec(precision), int(n_tmpl), int(n_seg)))
+    if nb == 0:
+        raise L.MfError(-1, _clib.mf_last_error().decode())
+    return nb
+
+
+def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, precision="fp32_ph64",
+           threshold: float = math.inf, window=None, series_units=None, workspace: torch.Tensor | None = None,
+           peaks: torch.Tensor | None = None):
+    """Peak rho, its index j and the threshold count for every (template, segment).
+
+    stilde: [n_seg, N/2+1] complex (complex128 for 'fp64', complex64 otherwise) on the GPU.
+    Returns dict(rho [n_tmpl, n_seg] float64, j int32, n_above int32, series or None).
+    """
+    prec = _prec(precision)
+    _require_cuda(stilde, Sn)
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous() or stilde.shape[-1] != grid.n // 2 + 1:
+        raise ValueError(f"stilde must be contiguous {_cdtype(prec)} of shape [n_seg, {grid.n // 2 + 1}]")
+    n_seg = int(stilde.shape[0])
+    dev = stilde.device
+    n_units = bank.n_tmpl * n_seg
+    need = filter_workspace_bytes(grid, prec, bank.n_tmpl, n_seg)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if peaks is None:
+        peaks = torch.empty(2 * n_units, dtype=torch.float64, device=dev)
+    opts = L.MfFilterOpts(float(threshold), 0, 0, None, 0)
+    if window is not None:
+        opts.j_begin, opts.j_end = int(window[0]), int(window[1])
+    series = None
+    su = None
+    if series_units is not None:
+        su = torch.as_tensor(np.asarray(series_units, dtype=np.int32), device=dev)
+        series = torch.empty((su.numel(), grid.n), dtype=torch.float64 if prec == L.MF_FP64 else torch.float32,
+                             device=dev)
+        opts.series_units_dev = su.data_ptr()
+        opts.n_series = su.numel()
+    g = grid.c()
+    st = _clib.mf_filter(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn), prec,
+                        C.byref(opts), _ptr(workspace), workspace.numel(), _ptr(peaks), _ptr(series), _stream(dev))
+    L.check(st)
+    pk = peaks.view(bank.n_tmpl, n_seg, 2)
+    ints = pk[..., 1].contiguous().view(torch.int32).view(bank.n_tmpl, n_seg, 2)
+    return {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "series": series}
+
+
+def ifft(q: torch.Tensor, precision="fp32_ph64", workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Unnormalised inverse DFT z_j = sum_k q_k e^{+2 pi i jk/N} over the last axis (diagnostic)."""
+    prec = _prec(precision)
+    _require_cuda(q)
+    if q.dtype != _cdtype(prec) or not q.is_contiguous():
+        raise ValueError(f"q must be contiguous {_cdtype(prec)}")
+    n = int(q.shape[-1])
+    batch = int(q.numel() // n)
+    need = int(_clib.mf_ifft_workspace_bytes(n, prec, batch))
+    if need == 0:
+        raise L.MfError(-2, _clib.mf_last_error().decode())
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=q.device)
+    z = torch.empty_like(q)
+    L.check(_clib.mf_ifft(n, prec, _ptr(q), _ptr(z), batch, _ptr(workspace), workspace.numel(), _stream(q.device)))
+    return z
+
+
+def snr_sq(grid: Grid, theta: torch.Tensor, seg: torch.Tensor, stilde: torch.Tensor, Sn: torch.Tensor,
+           khi: torch.Tensor | None = None, precision="fp32_ph64", gbar: torch.Tensor | None = None):
+    """F = rho^2 at theta = [n, 3] (M_c [M_sun], eta, t_c [s]); with gbar also gbar * dF/dtheta."""
+    prec = _prec(precision)
+    _require_cuda(theta, seg, stilde, Sn, khi, gbar)
+    theta = theta.to(torch.float64).contiguous()
+    seg = seg.to(torch.int32).contiguous()
+    if khi is not None:
+        khi = khi.to(torch.int32).contiguous()
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous():
+        raise ValueError(f"stilde must be contiguous {_cdtype(prec)}")
+    n = int(theta.shape[0])
+    dev = theta.device
+    Z = torch.empty(n, dtype=torch.complex128, device=dev)
+    F = torch.empty(n, dtype=torch.float64, device=dev)
+    grad = None
+    if gbar is not None:
+        gbar = gbar.to(torch.float64).contiguous()
+        grad = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    g = grid.c()
+    st = _clib.mf_snr_grad(C.byref(g), _ptr(theta), _ptr(khi), _ptr(seg), n, _ptr(stilde), int(stilde.shape[0]),
+                          _ptr(Sn), prec, _ptr(Z), _ptr(F), _ptr(gbar), _ptr(grad), _stream(dev))
+    L.check(st)
+    return F, Z, grad
+
+
+class SnrSq(torch.autograd.Function):
+    """rho^2(theta) with the hand-written adjoint kernel as its backward."""
+
+    @staticmethod
+    def forward(ctx, theta, grid, seg, stilde, Sn, khi=None, precision="fp32_ph64"):
+        F, Z, _ = snr_sq(grid, theta.detach(), seg, stilde, Sn, khi, precision)
+        ctx.save_for_backward(theta.detach(), seg, stilde, Sn, khi if khi is not None else torch.empty(0))
+        ctx.grid = grid
+        ctx.precision = precision
+        ctx.has_khi = khi is not None
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        theta, seg, stilde, Sn, khi = ctx.saved_tensors
+        _, _, grad = snr_sq(ctx.grid, theta, seg, stilde, Sn, khi if ctx.has_khi else None, ctx.precision,
+                            gbar=gF.contiguous())
+        return grad, None, None, None, None, None, None

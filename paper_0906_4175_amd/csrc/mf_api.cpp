@@ -1,0 +1,389 @@
+// extern "C" entry points of libmf (include/mf.h): argument validation,
+// host-side FP64 template coefficients and band edges, workspace carve-up and
+// the launch sequence of the matched filter.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "mf_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+// Measurement hook state (event pairs around sampled pass launches).
+struct TimedLaunch {
+    hipEvent_t start, stop;
+    int pass;
+    int64_t units;
+};
+struct TimingState {
+    int32_t stride = 0;
+    int64_t batch_counter = 0;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> pool;
+};
+TimingState g_timing;
+
+hipEvent_t timing_event() {
+    if (!g_timing.pool.empty()) {
+        hipEvent_t e = g_timing.pool.back();
+        g_timing.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+mf_status fail(mf_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+mf_status ok() {
+    g_err.clear();
+    return MF_OK;
+}
+
+mf_status hip_fail(hipError_t e, const char* where) {
+    return fail(MF_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool valid_prec(mf_precision p) { return p == MF_FP64 || p == MF_FP32_PH64 || p == MF_FP32; }
+
+int log2_exact(int64_t n) {
+    if (n <= 0 || (n & (n - 1)) != 0) return -1;
+    int l = 0;
+    while ((int64_t(1) << l) < n) ++l;
+    return l;
+}
+
+// Validates the grid; k_lo = ceil(f_low T) is the first band bin.
+mf_status check_grid(const mf_grid* g, int* log2n, int* k_lo) {
+    if (!g) return fail(MF_E_ARG, "grid is null");
+    const int l = log2_exact(g->n);
+    if (l < mf::kMinLog2N || l > mf::kMaxLog2N)
+        return fail(MF_E_SHAPE, "n=%lld must be a power of two in [2^%d, 2^%d]", (long long)g->n, mf::kMinLog2N,
+                    mf::kMaxLog2N);
+    if (!(g->fs > 0.0) || !isfinite(g->fs)) return fail(MF_E_ARG, "fs=%g must be positive and finite", g->fs);
+    if (!(g->f0 > 0.0) || !isfinite(g->f0)) return fail(MF_E_ARG, "f0=%g must be positive and finite", g->f0);
+    if (!(g->f_low > 0.0) || !(g->f_low < 0.5 * g->fs))
+        return fail(MF_E_BAND, "f_low=%g must lie in (0, fs/2=%g)", g->f_low, 0.5 * g->fs);
+    const double T = (double)g->n / g->fs;
+    const double kl = ceil(g->f_low * T);
+    if (kl < 1.0 || kl > (double)(g->n / 2 - 1))
+        return fail(MF_E_BAND, "f_low=%g gives first bin %g outside [1, N/2-1]", g->f_low, kl);
+    *log2n = l;
+    *k_lo = (int)kl;
+    return MF_OK;
+}
+
+// Upper band edge: min(floor(f_ISCO T), N/2 - 1), f_ISCO = 1/(6^{3/2} pi M).
+int64_t band_hi(const mf_grid* g, double mc, double eta) {
+    const double m_total = mc * pow(eta, -0.6);
+    const double M = m_total * mf::kTsun;
+    const double fisco = 1.0 / (sqrt(216.0) * M_PI * M);
+    const double T = (double)g->n / g->fs;
+    const double kh = floor(fisco * T);
+    const double cap = (double)(g->n / 2 - 1);
+    return (int64_t)(kh < cap ? kh : cap);
+}
+
+// FP64 coefficients of the stationary-phase phase in cycles, as a power
+// series in u = k^{-1/3}:  Psi/2pi = b1 u + b2 u^2 + b3 u^3 + b5 u^5 - 1/8.
+// With v = (pi M f)^{1/3} and f = k df, 3/(128 eta v^5) v^n = C (pi M df)^{(n-5)/3} u^{5-n}.
+void spa_coefficients(double mc, double eta, double df, mf_bank_entry* e) {
+    const double M = mc * pow(eta, -0.6) * mf::kTsun;
+    const double x = M_PI * M * df;
+    const double C = 3.0 / (128.0 * eta);
+    const double inv2pi = 0.5 / M_PI;
+    const double p2 = 3715.0 / 756.0 + 55.0 * eta / 9.0;
+    const double p3 = -16.0 * M_PI;
+    const double p4 = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * eta * eta / 72.0;
+    e->b5 = C * pow(x, -5.0 / 3.0) * inv2pi;
+    e->b3 = C * p2 / x * inv2pi;
+    e->b2 = C * p3 * pow(x, -2.0 / 3.0) * inv2pi;
+    e->b1 = C * p4 * pow(x, -1.0 / 3.0) * inv2pi;
+    e->c0 = -0.125;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mf_last_error(void) { return g_err.c_str(); }
+
+const char* mf_version(void) { return "libmf 0.1.0 gfx950"; }
+
+size_t mf_bank_bytes(int64_t n_tmpl) { return n_tmpl > 0 ? (size_t)n_tmpl * sizeof(mf_bank_entry) : 0; }
+
+size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl, int64_t n_seg) {
+    int l, klo;
+    if (check_grid(grid, &l, &klo) != MF_OK) return 0;
+    if (!valid_prec(prec) || n_tmpl < 1 || n_seg < 1) {
+        fail(MF_E_ARG, "bad precision or counts");
+        return 0;
+    }
+    const mf::Plan p = mf::default_plan(l, prec);
+    return mf::filter_layout(p, prec, grid->n, n_tmpl, n_seg).total;
+}
+
+mf_status mf_psd(const mf_grid* grid, double* Sn_dev, double* prefix_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!Sn_dev) return fail(MF_E_ARG, "Sn_dev is null");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = mf::launch_psd(grid->n, grid->fs, grid->f_low, grid->f0, klo, Sn_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_psd");
+    if (prefix_dev) {
+        e = mf::launch_prefix(grid->n, grid->fs, Sn_dev, prefix_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_psd prefix");
+    }
+    return ok();
+}
+
+mf_status mf_spa_bank(const mf_grid* grid, const double* mc_host, const double* eta_host, int64_t n_tmpl,
+                      const double* Sn_dev, mf_precision prec, mf_sigma_mode sigma_mode, void* bank_dev,
+                      int32_t* khi_host, double* sigma_host, void* htilde_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!mc_host || !eta_host || !Sn_dev || !bank_dev) return fail(MF_E_ARG, "null pointer argument");
+    if (n_tmpl < 1 || n_tmpl > (int64_t(1) << 31) - 1) return fail(MF_E_ARG, "n_tmpl=%lld", (long long)n_tmpl);
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (sigma_mode != MF_SIGMA_FP64 && sigma_mode != MF_SIGMA_COMP32)
+        return fail(MF_E_ARG, "bad sigma mode %d", (int)sigma_mode);
+    if (htilde_dev && n_tmpl > 65535) return fail(MF_E_ARG, "materialised templates limited to 65535");
+    const double df = grid->fs / (double)grid->n;
+    std::vector<mf_bank_entry> h((size_t)n_tmpl);
+    for (int64_t t = 0; t < n_tmpl; ++t) {
+        const double mc = mc_host[t], eta = eta_host[t];
+        if (!(mc > 0.0) || !isfinite(mc)) return fail(MF_E_ARG, "template %lld: chirp mass %g", (long long)t, mc);
+        if (!(eta > 0.0) || !(eta <= 0.25)) return fail(MF_E_ARG, "template %lld: eta %g", (long long)t, eta);
+        mf_bank_entry& e = h[(size_t)t];
+        e = mf_bank_entry{};
+        spa_coefficients(mc, eta, df, &e);
+        e.k_lo = klo;
+        const int64_t khi = band_hi(grid, mc, eta);
+        if (khi < klo)
+            return fail(MF_E_BAND, "template %lld: empty band (k_hi=%lld < k_lo=%d)", (long long)t, (long long)khi, klo);
+        e.k_hi = (int32_t)khi;
+        if (khi_host) khi_host[t] = (int32_t)khi;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(bank_dev, h.data(), h.size() * sizeof(mf_bank_entry), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_spa_bank copy");
+    e = mf::launch_sigma(grid->n, grid->fs, sigma_mode, Sn_dev, (mf_bank_entry*)bank_dev, n_tmpl, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_spa_bank sigma");
+    if (htilde_dev) {
+        e = mf::launch_spa_synth(grid->n, grid->fs, prec, (const mf_bank_entry*)bank_dev, n_tmpl, htilde_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_spa_bank synth");
+    }
+    if (sigma_host) {
+        e = hipMemcpyAsync(h.data(), bank_dev, h.size() * sizeof(mf_bank_entry), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_spa_bank sigma copy");
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "mf_spa_bank sync");
+    if (sigma_host)
+        for (int64_t t = 0; t < n_tmpl; ++t) sigma_host[t] = h[(size_t)t].sigma;
+    return ok();
+}
+
+mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev, int64_t n_seg,
+                    const double* Sn_dev, mf_precision prec, const mf_filter_opts* opts, void* workspace_dev,
+                    size_t workspace_bytes, mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!bank_dev || !stilde_dev || !Sn_dev || !peaks_dev || !workspace_dev)
+        return fail(MF_E_ARG, "null pointer argument");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (n_tmpl < 1 || n_seg < 1) return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld", (long long)n_tmpl, (long long)n_seg);
+    if (n_tmpl * n_seg > (int64_t(1) << 40)) return fail(MF_E_ARG, "too many units");
+    const int64_t n = grid->n;
+    mf_filter_opts o{INFINITY, 0, 0, nullptr, 0};
+    if (opts) o = *opts;
+    if (o.j_end == 0) o.j_end = n;
+    if (o.j_begin < 0 || o.j_end > n || o.j_begin >= o.j_end)
+        return fail(MF_E_SHAPE, "window [%lld, %lld) outside [0, %lld)", (long long)o.j_begin, (long long)o.j_end,
+                    (long long)n);
+    if (o.rho_threshold != o.rho_threshold) return fail(MF_E_ARG, "rho_threshold is NaN");
+    if (o.n_series < 0) return fail(MF_E_ARG, "n_series < 0");
+    if (o.n_series > 0 && (!o.series_units_dev || !rho_dev))
+        return fail(MF_E_ARG, "series requested without series_units_dev / rho_dev");
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(MF_E_ARG, "workspace must be 256-byte aligned");
+    const mf::Plan p = mf::default_plan(l, prec);
+    if (p.log2n != l || (int64_t)p.n1 * p.n2 != n || p.n2 % p.c1 != 0 || p.n1 % p.b2 != 0)
+        return fail(MF_E_UNSUPPORTED, "no plan for n=%lld", (long long)n);
+    const mf::FilterLayout L = mf::filter_layout(p, prec, n, n_tmpl, n_seg);
+    if (workspace_bytes < L.total)
+        return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+
+    char* ws = (char*)workspace_dev;
+    mf::FilterArgs a{};
+    a.wgt = ws + L.off_w;
+    a.bank = (const mf_bank_entry*)bank_dev;
+    a.inter = ws + L.off_inter;
+    a.keys = prec == MF_FP64 ? nullptr : (unsigned long long*)(ws + L.off_keys);
+    a.counts = prec == MF_FP64 ? nullptr : (unsigned int*)(ws + L.off_counts);
+    a.partials = prec == MF_FP64 ? (void*)(ws + L.off_part) : nullptr;
+    a.n_tmpl = n_tmpl;
+    a.n_seg = n_seg;
+    a.n_units = n_tmpl * n_seg;
+    a.j_begin = o.j_begin;
+    a.j_end = o.j_end;
+    a.rho_threshold = o.rho_threshold;
+    a.series_units = o.series_units_dev;
+    a.n_series = o.n_series;
+    a.rho = rho_dev;
+
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter weights");
+    for (int64_t u0 = 0; u0 < a.n_units; u0 += L.units_per_batch) {
+        a.unit0 = u0;
+        a.units = (a.n_units - u0) < L.units_per_batch ? (a.n_units - u0) : L.units_per_batch;
+        const bool timed = g_timing.stride > 0 && (g_timing.batch_counter++ % g_timing.stride) == 0;
+        TimedLaunch t1{}, t2{};
+        if (timed) {
+            t1 = TimedLaunch{timing_event(), timing_event(), 1, a.units};
+            t2 = TimedLaunch{timing_event(), timing_event(), 2, a.units};
+            if (!t1.start || !t1.stop || !t2.start || !t2.stop) return fail(MF_E_HIP, "timing event creation failed");
+            hipEventRecord(t1.start, s);
+        }
+        e = mf::launch_pass1(p, prec, false, a, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_filter pass1");
+        if (timed) {
+            hipEventRecord(t1.stop, s);
+            hipEventRecord(t2.start, s);
+        }
+        e = mf::launch_pass2(p, prec, false, a, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_filter pass2");
+        if (timed) {
+            hipEventRecord(t2.stop, s);
+            g_timing.pending.push_back(t1);
+            g_timing.pending.push_back(t2);
+        }
+        if (prec == MF_FP64) {
+            e = mf::launch_finalize(p, prec, a, peaks_dev, s);
+            if (e != hipSuccess) return hip_fail(e, "mf_filter finalize");
+        }
+    }
+    if (prec != MF_FP64) {
+        e = mf::launch_finalize(p, prec, a, peaks_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_filter finalize");
+    }
+    return ok();
+}
+
+size_t mf_ifft_workspace_bytes(int64_t n, mf_precision prec, int64_t batch) {
+    const int l = log2_exact(n);
+    if (l < mf::kMinLog2N || l > mf::kMaxLog2N || !valid_prec(prec) || batch < 1) {
+        fail(MF_E_ARG, "bad n/precision/batch");
+        return 0;
+    }
+    const mf::Plan p = mf::default_plan(l, prec);
+    const int64_t u = batch < p.units ? batch : p.units;
+    return (size_t)u * (size_t)n * mf::cx_bytes(prec);
+}
+
+mf_status mf_ifft(int64_t n, mf_precision prec, const void* q_dev, void* z_dev, int64_t batch, void* workspace_dev,
+                  size_t workspace_bytes, mf_stream_t stream) {
+    const int l = log2_exact(n);
+    if (l < mf::kMinLog2N || l > mf::kMaxLog2N)
+        return fail(MF_E_SHAPE, "n=%lld must be a power of two in [2^%d, 2^%d]", (long long)n, mf::kMinLog2N,
+                    mf::kMaxLog2N);
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (!q_dev || !z_dev || !workspace_dev) return fail(MF_E_ARG, "null pointer argument");
+    if (batch < 1) return fail(MF_E_ARG, "batch=%lld", (long long)batch);
+    const size_t need = mf_ifft_workspace_bytes(n, prec, batch);
+    if (workspace_bytes < need) return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, need);
+    const mf::Plan p = mf::default_plan(l, prec);
+    const int64_t upb = batch < p.units ? batch : p.units;
+    mf::FilterArgs a{};
+    a.inter = workspace_dev;
+    a.raw_in = q_dev;
+    a.raw_out = z_dev;
+    a.n_tmpl = 1;
+    a.n_seg = batch;
+    a.n_units = batch;
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t u0 = 0; u0 < batch; u0 += upb) {
+        a.unit0 = u0;
+        a.units = (batch - u0) < upb ? (batch - u0) : upb;
+        hipError_t e = mf::launch_pass1(p, prec, true, a, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_ifft pass1");
+        e = mf::launch_pass2(p, prec, true, a, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_ifft pass2");
+    }
+    return ok();
+}
+
+mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_t* khi_dev, const int32_t* seg_dev,
+                      int64_t n, const void* stilde_dev, int64_t n_seg, const double* Sn_dev, mf_precision prec,
+                      double* Z_dev, double* rho2_dev, const double* gbar_dev, double* grad_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!theta_dev || !seg_dev || !stilde_dev || !Sn_dev || !Z_dev || !rho2_dev)
+        return fail(MF_E_ARG, "null pointer argument");
+    if (gbar_dev && !grad_dev) return fail(MF_E_ARG, "gbar_dev given without grad_dev");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (n < 1 || n > (int64_t(1) << 31) - 1 || n_seg < 1) return fail(MF_E_ARG, "n=%lld n_seg=%lld", (long long)n,
+                                                                       (long long)n_seg);
+    hipError_t e = mf::launch_snr_grad(grid->n, grid->fs, klo, prec, theta_dev, khi_dev, seg_dev, n, stilde_dev, n_seg, Sn_dev,
+                                       Z_dev, rho2_dev, gbar_dev, grad_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mf_snr_grad");
+    return ok();
+}
+
+mf_status mf_timing_enable(int32_t stride) {
+    if (stride < 0) return fail(MF_E_ARG, "stride < 0");
+    g_timing.stride = stride;
+    g_timing.batch_counter = 0;
+    return ok();
+}
+
+mf_status mf_timing_read(double* pass1_ms, int64_t* pass1_launches, int64_t* pass1_units, double* pass2_ms,
+                         int64_t* pass2_launches, int64_t* pass2_units) {
+    if (!pass1_ms || !pass1_launches || !pass1_units || !pass2_ms || !pass2_launches || !pass2_units)
+        return fail(MF_E_ARG, "null pointer argument");
+    double ms[3] = {0, 0, 0};
+    int64_t cnt[3] = {0, 0, 0}, units[3] = {0, 0, 0};
+    mf_status st = MF_OK;
+    for (const TimedLaunch& t : g_timing.pending) {
+        hipError_t e = hipEventSynchronize(t.stop);
+        float el = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&el, t.start, t.stop);
+        if (e != hipSuccess && st == MF_OK) st = hip_fail(e, "mf_timing_read");
+        ms[t.pass] += el;
+        cnt[t.pass] += 1;
+        units[t.pass] += t.units;
+        g_timing.pool.push_back(t.start);
+        g_timing.pool.push_back(t.stop);
+    }
+    g_timing.pending.clear();
+    *pass1_ms = ms[1];
+    *pass1_launches = cnt[1];
+    *pass1_units = units[1];
+    *pass2_ms = ms[2];
+    *pass2_launches = cnt[2];
+    *pass2_units = units[2];
+    return st == MF_OK ? ok() : st;
+}
+
+}  // extern "C"

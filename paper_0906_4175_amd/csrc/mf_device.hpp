@@ -1,0 +1,222 @@
+// Device building blocks shared by the libmf kernels: complex arithmetic,
+// constant-size inverse DFTs held in registers, and the stationary-phase
+// template rotor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mf.h"
+
+namespace mf {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by +i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------------------
+// Inverse DFT of R points in registers: v_u <- sum_r v_r e^{+2 pi i u r / R}.
+// Radix-2 decimation in time down to a hand-written 4-point kernel; the
+// twiddles are compile-time roots of unity (R <= 16).
+// ---------------------------------------------------------------------------
+struct Roots16 {
+    // cos and sin of 2 pi u / 16, u = 0..7
+    static constexpr double c[8] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                                    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674};
+    static constexpr double s[8] = {0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674,
+                                    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977};
+};
+
+// multiply by e^{+2 pi i u / R} with compile-time u, R
+template <int U, int R, typename T>
+__device__ __forceinline__ cx<T> rot(cx<T> a) {
+    constexpr int q = (U * 16 / R) % 16;  // index in 16th roots
+    if constexpr (q == 0) {
+        return a;
+    } else if constexpr (q == 4) {
+        return mul_i(a);
+    } else if constexpr (q == 8) {
+        return cx<T>{-a.x, -a.y};
+    } else if constexpr (q == 12) {
+        return cx<T>{a.y, -a.x};
+    } else if constexpr (q == 2 || q == 6 || q == 10 || q == 14) {
+        // (+-1 +- i)/sqrt(2) multiples: 2 multiplies
+        constexpr T h = T(0.70710678118654752);
+        constexpr T cr = (q == 2 || q == 14) ? h : -h;
+        constexpr T sr = (q == 2 || q == 6) ? h : -h;
+        return cx<T>{(a.x * cr) - (a.y * sr), (a.x * sr) + (a.y * cr)};
+    } else {
+        constexpr T cr = q < 8 ? T(Roots16::c[q]) : T(Roots16::c[q - 8]) * T(-1);
+        constexpr T sr = q < 8 ? T(Roots16::s[q]) : T(Roots16::s[q - 8]) * T(-1);
+        return cx<T>{a.x * cr - a.y * sr, a.x * sr + a.y * cr};
+    }
+}
+
+template <int R, typename T>
+struct IDft;
+
+template <typename T>
+struct IDft<1, T> {
+    __device__ __forceinline__ static void run(cx<T>*) {}
+};
+
+template <typename T>
+struct IDft<2, T> {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    }
+};
+
+template <typename T>
+struct IDft<4, T> {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        cx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
+        cx<T> s13 = v[1] + v[3], d13 = mul_i(v[1] - v[3]);
+        v[0] = s02 + s13;
+        v[2] = s02 - s13;
+        v[1] = d02 + d13;
+        v[3] = d02 - d13;
+    }
+};
+
+template <int R, typename T>
+struct IDft {
+    template <int U>
+    __device__ __forceinline__ static void combine(cx<T>* v, cx<T>* e, cx<T>* o) {
+        if constexpr (U < R / 2) {
+            cx<T> t = rot<U, R>(o[U]);
+            v[U] = e[U] + t;
+            v[U + R / 2] = e[U] - t;
+            combine<U + 1>(v, e, o);
+        }
+    }
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) {
+            e[r] = v[2 * r];
+            o[r] = v[2 * r + 1];
+        }
+        IDft<R / 2, T>::run(e);
+        IDft<R / 2, T>::run(o);
+        combine<0>(v, e, o);
+    }
+};
+
+// Radix of stage s for an L-point transform: 16 while at least 16 remains,
+// then the remainder.
+__host__ __device__ constexpr int radix_at(int L, int s) {
+    int rem = L;
+    for (int i = 0; i < s; ++i) rem /= (rem >= 16 ? 16 : rem);
+    return rem >= 16 ? 16 : rem;
+}
+__host__ __device__ constexpr int num_stages(int L) {
+    int n = 0;
+    for (int rem = L; rem > 1; rem /= (rem >= 16 ? 16 : rem)) ++n;
+    return n;
+}
+__host__ __device__ constexpr int span_before(int L, int s) {
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= radix_at(L, i);
+    return ns;
+}
+__host__ __device__ constexpr int ilog2(long long x) {
+    int r = 0;
+    while ((1LL << r) < x) ++r;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Accurate roots of unity e^{+2 pi i m / M} from an exact dyadic argument.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cx<float> root_of_unity(float frac) {
+    float s, c;
+    sincospif(2.0f * frac, &s, &c);
+    return {c, s};
+}
+__device__ __forceinline__ cx<double> root_of_unity(double frac) {
+    double s, c;
+    sincospi(2.0 * frac, &s, &c);
+    return {c, s};
+}
+
+// ---------------------------------------------------------------------------
+// Stationary-phase template rotor e^{+i Psi_k} for bin k.
+//   Psi_k / 2 pi = b1 u + b2 u^2 + b3 u^3 + b5 u^5 + c0 + bt k,  u = k^(-1/3)
+// In the FP64-phase modes u comes from an FP32 estimate refined by two
+// Newton steps in FP64 (quadratic convergence from ~1e-7 to full precision),
+// the polynomial is evaluated in FP64 and reduced exactly to [-1/2, 1/2]
+// cycles (subtracting the nearest integer is exact), and only the reduced
+// fraction is rounded to the FFT precision before sin/cos.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double inv_cbrt_f64(double kd) {
+    float kf = (float)kd;
+    double u = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(kf) * (-1.0f / 3.0f));
+    // Newton on g(u) = u^-3 - k:  u <- u + u (1 - k u^3) / 3
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        double u3 = u * u * u;
+        double r = fma(-kd, u3, 1.0);
+        u = fma(u * r, 1.0 / 3.0, u);
+    }
+    return u;
+}
+
+struct PhaseCoef {
+    double b1, b2, b3, b5, c0, bt;
+};
+
+__device__ __forceinline__ double spa_cycles_f64(const PhaseCoef& p, double kd) {
+    double u = inv_cbrt_f64(kd);
+    double uu = u * u;
+    double poly = u * fma(u, fma(u, fma(uu, p.b5, p.b3), p.b2), p.b1);
+    return poly + fma(p.bt, kd, p.c0);
+}
+
+// FP64 phase, rotor in precision T
+template <typename T>
+__device__ __forceinline__ cx<T> spa_rotor_ph64(const PhaseCoef& p, double kd) {
+    double ph = spa_cycles_f64(p, kd);
+    ph -= rint(ph);
+    return root_of_unity((T)ph);
+}
+
+// FP32 phase throughout (precision study): u, polynomial and reduction in FP32.
+__device__ __forceinline__ cx<float> spa_rotor_ph32(const PhaseCoef& p, float kf) {
+    float u = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(kf) * (-1.0f / 3.0f));
+    // one FP32 Newton step brings the hardware estimate to ~1 ulp
+    float u3 = u * u * u;
+    u = fmaf(u * fmaf(-kf, u3, 1.0f), 1.0f / 3.0f, u);
+    float uu = u * u;
+    float poly = u * fmaf(u, fmaf(u, fmaf(uu, (float)p.b5, (float)p.b3), (float)p.b2), (float)p.b1);
+    float ph = poly + fmaf((float)p.bt, kf, (float)p.c0);
+    ph -= rintf(ph);
+    return root_of_unity(ph);
+}
+
+__device__ __forceinline__ PhaseCoef load_coef(const mf_bank_entry& e) {
+    return PhaseCoef{e.b1, e.b2, e.b3, e.b5, e.c0, 0.0};
+}
+
+}  // namespace mf

@@ -1,0 +1,77 @@
+// Host-side internals of libmf: launch plans, workspace layout, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mf.h"
+
+namespace mf {
+
+constexpr double kTsun = 4.925490947641267e-6;  // G M_sun / c^3 [s] (IAU 2015 nominal)
+constexpr int kMinLog2N = 10;
+constexpr int kMaxLog2N = 22;
+
+// Two-pass decomposition N = n1 * n2 of the inverse DFT and the work-group
+// shapes of the two passes.
+struct Plan {
+    int log2n;
+    int n1, n2;      // column length (pass 1) and row length (pass 2)
+    int c1;          // columns per pass-1 work-group
+    int nt1;         // threads per pass-1 work-group
+    int b2;          // rows per pass-2 work-group
+    int nt2;         // threads per pass-2 work-group
+    int units;       // (template, segment) units whose intermediate is in flight
+};
+
+Plan default_plan(int log2n, mf_precision prec);
+
+size_t cx_bytes(mf_precision prec);
+
+// Workspace carve-up of mf_filter.
+struct FilterLayout {
+    size_t off_w, off_inter, off_keys, off_counts, off_part, total;
+    int64_t units_per_batch;
+};
+FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg);
+
+struct FilterArgs {
+    const void* wgt;          // [n_seg][n/2+1] weighted data
+    const mf_bank_entry* bank;
+    void* inter;              // [units][n]
+    unsigned long long* keys; // [n_units] (FP32 modes)
+    unsigned int* counts;     // [n_units] (FP32 modes)
+    void* partials;           // [units][n1/b2] (FP64)
+    int64_t n_tmpl, n_seg, n_units;
+    int64_t unit0, units;     // batch
+    int64_t j_begin, j_end;
+    double rho_threshold;
+    const int32_t* series_units;
+    int32_t n_series;
+    void* rho;                // series output
+    const void* raw_in;       // mf_ifft input  [units][n]
+    void* raw_out;            // mf_ifft output [units][n]
+};
+
+// Launchers (return hipError_t of the launch)
+hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
+hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
+hipError_t launch_finalize(const Plan& p, mf_precision prec, const FilterArgs& a, mf_peak* peaks, hipStream_t s);
+
+hipError_t launch_psd(int64_t n, double fs, double f_low, double f0, int k_lo, double* Sn, hipStream_t s);
+hipError_t launch_prefix(int64_t n, double fs, const double* Sn, double* prefix, hipStream_t s);
+hipError_t launch_weights(int64_t n, double fs, int k_lo, mf_precision prec, const void* stilde, int64_t n_seg,
+                          const double* Sn, void* wgt, hipStream_t s);
+hipError_t launch_sigma(int64_t n, double fs, mf_sigma_mode mode, const double* Sn, mf_bank_entry* bank,
+                        int64_t n_tmpl, hipStream_t s);
+hipError_t launch_spa_synth(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
+                            void* htilde, hipStream_t s);
+hipError_t launch_snr_grad(int64_t n, double fs, int k_lo, mf_precision prec, const double* theta,
+                           const int32_t* khi, const int32_t* seg, int64_t count, const void* stilde,
+                           int64_t n_seg, const double* Sn, double* Z, double* rho2, const double* gbar, double* grad,
+                           hipStream_t s);
+
+}  // namespace mf

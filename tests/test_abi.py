@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments before enqueueing any device work."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_0906_4175_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mf_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ["mf_psd", "mf_spa_bank", "mf_filter", "mf_snr_grad", "mf_last_error",
+                     "mf_filter_workspace_bytes", "mf_bank_bytes"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mf_[a-z_0-9]+)", out))
+    for name in _declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_struct_sizes_match_header(lib):
+    assert C.sizeof(L.MfBankEntry) == 64
+    assert C.sizeof(L.MfPeak) == 16
+    assert int(lib.mf_bank_bytes(10)) == 640
+    assert int(lib.mf_bank_bytes(0)) == 0
+
+
+def _grid(n=1 << 20, fs=4096.0, f_low=40.0, f0=150.0):
+    return L.MfGrid(n, fs, f_low, f0)
+
+
+@pytest.mark.parametrize("n", [1000, 1 << 9, 1 << 23, 0, -4])
+def test_bad_length_rejected(lib, n):
+    g = _grid(n=n)
+    assert lib.mf_psd(C.byref(g), C.c_void_p(16), None, None) == -2
+    assert b"power of two" in lib.mf_last_error()
+
+
+@pytest.mark.parametrize("f_low", [0.0, -1.0, 2048.0, 5000.0, math.nan])
+def test_bad_band_rejected(lib, f_low):
+    g = _grid(f_low=f_low)
+    assert lib.mf_psd(C.byref(g), C.c_void_p(16), None, None) == -3
+
+
+def test_null_pointers_rejected(lib):
+    g = _grid()
+    assert lib.mf_psd(C.byref(g), None, None, None) == -1
+    assert lib.mf_psd(None, C.c_void_p(16), None, None) == -1
+    peaks = C.c_void_p(16)
+    assert lib.mf_filter(C.byref(g), None, 1, C.c_void_p(16), 1, C.c_void_p(16), 1, None,
+                         C.c_void_p(256), 1 << 30, peaks, None, None) == -1
+
+
+def test_bank_parameter_validation(lib):
+    g = _grid()
+    mc = (C.c_double * 2)(1.2, 1.2)
+    for eta_bad in (0.0, 0.26, -0.1, math.nan):
+        eta = (C.c_double * 2)(0.25, eta_bad)
+        st = lib.mf_spa_bank(C.byref(g), mc, eta, 2, C.c_void_p(16), 1, 0, C.c_void_p(256), None, None, None, None)
+        assert st == -1
+        assert b"template 1" in lib.mf_last_error()
+    eta = (C.c_double * 2)(0.25, 0.25)
+    mcb = (C.c_double * 2)(1.2, 0.0)
+    assert lib.mf_spa_bank(C.byref(g), mcb, eta, 2, C.c_void_p(16), 1, 0, C.c_void_p(256), None, None, None,
+                           None) == -1
+    # A 60+60 M_sun template has f_ISCO ~ 37 Hz < f_low: empty band, index named.
+    mch = (C.c_double * 2)(1.2, 52.2)
+    st = lib.mf_spa_bank(C.byref(g), mch, eta, 2, C.c_void_p(16), 1, 0, C.c_void_p(256), None, None, None, None)
+    assert st == -3
+    assert b"template 1" in lib.mf_last_error()
+    # bad enums
+    assert lib.mf_spa_bank(C.byref(g), mc, eta, 2, C.c_void_p(16), 7, 0, C.c_void_p(256), None, None, None,
+                           None) == -1
+    assert lib.mf_spa_bank(C.byref(g), mc, eta, 2, C.c_void_p(16), 1, 5, C.c_void_p(256), None, None, None,
+                           None) == -1
+
+
+def test_filter_workspace_and_window_validation(lib):
+    g = _grid()
+    need = int(lib.mf_filter_workspace_bytes(C.byref(g), 1, 1024, 1))
+    # w (4 MiB) + intermediates + peak keys
+    assert need >= (1 << 20) // 2 * 8 + 8 * (1 << 20) * 8
+    args = lambda ws, opts=None, wsp=256: (C.byref(g), C.c_void_p(256), 1024, C.c_void_p(256), 1, C.c_void_p(256),
+                                            1, opts, C.c_void_p(wsp), ws, C.c_void_p(256), None, None)
+    assert lib.mf_filter(*args(need - 1)) == -5
+    assert b"workspace" in lib.mf_last_error()
+    assert lib.mf_filter(*args(need, wsp=264)) == -1  # misaligned workspace
+    bad = L.MfFilterOpts(math.inf, 10, 5, None, 0)
+    assert lib.mf_filter(*args(need, C.byref(bad))) == -2
+    bad = L.MfFilterOpts(math.inf, 0, (1 << 20) + 1, None, 0)
+    assert lib.mf_filter(*args(need, C.byref(bad))) == -2
+    bad = L.MfFilterOpts(math.inf, 0, 0, None, 3)
+    assert lib.mf_filter(*args(need, C.byref(bad))) == -1
+    bad = L.MfFilterOpts(math.nan, 0, 0, None, 0)
+    assert lib.mf_filter(*args(need, C.byref(bad))) == -1
+    assert lib.mf_filter(*args(need)[:6], 9, *args(need)[7:]) == -1  # bad precision
+
+
+def test_ifft_and_grad_validation(lib):
+    assert lib.mf_ifft_workspace_bytes(1000, 1, 1) == 0
+    assert lib.mf_ifft(1 << 12, 1, None, C.c_void_p(256), 1, C.c_void_p(256), 1 << 20, None) == -1
+    assert lib.mf_ifft(1 << 12, 1, C.c_void_p(256), C.c_void_p(256), 2, C.c_void_p(256), 10, None) == -5
+    g = _grid()
+    assert lib.mf_snr_grad(C.byref(g), None, None, C.c_void_p(256), 1, C.c_void_p(256), 1, C.c_void_p(256), 1,
+                           C.c_void_p(256), C.c_void_p(256), None, None, None) == -1
+    assert lib.mf_snr_grad(C.byref(g), C.c_void_p(256), None, C.c_void_p(256), 1, C.c_void_p(256), 1,
+                           C.c_void_p(256), 1, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256), None, None) == -1
