@@ -120,6 +120,14 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
                                  int64_t n_tmpl, int64_t n_seg);
 
 /*
+ * The launch plan mf_filter uses for this grid and precision (after any
+ * tuning): plan[0..7] = {N1, N2, columns per pass-1 work-group, rows per
+ * pass-2 work-group, pass-1 threads, pass-2 threads, units per batch,
+ * 1 if pass 1 of batch b and pass 2 of batch b-1 share a launch}.
+ */
+mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
+
+/*
  * mf_psd -- Eq. (2) on the one-sided bins (setup call).
  *   Sn_dev     [N/2+1] double, written: S_n(k df) for k_lo <= k <= N/2-1,
  *              +inf at the other bins (DC, below f_low, Nyquist), so that
@@ -209,15 +217,24 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
 
 /*
  * Measurement hook (not part of the method).  With stride > 0, mf_filter
- * records a HIP event pair on its stream around the pass-1 and pass-2
- * launches of every stride-th batch; mf_timing_read waits for the recorded
- * events, returns the summed kernel durations [ms], launch counts and summed
- * (template, segment) units of the sampled launches, and clears the record.
- * stride = 0 disables recording.  Host state only; not thread-safe.
+ * records a HIP event pair on its stream around every stride-th launch of its
+ * transform kernels; mf_timing_read waits for the recorded events and returns
+ * their summed duration [ms], the number of timed launches, and the
+ * (template, segment) units whose pass 1 (template x weight product, column
+ * transforms, intermediate store) and pass 2 (row transforms, |z| peak) those
+ * launches processed; it then clears the record.  stride = 0 disables
+ * recording.  Host state only; not thread-safe.
  */
 mf_status mf_timing_enable(int32_t stride);
-mf_status mf_timing_read(double* pass1_ms, int64_t* pass1_launches, int64_t* pass1_units,
-                         double* pass2_ms, int64_t* pass2_launches, int64_t* pass2_units);
+mf_status mf_timing_read(double* ms, int64_t* launches, int64_t* pass1_units, int64_t* pass2_units);
+
+/*
+ * Calibration kernel (not part of the method): copies `bytes` (a non-zero
+ * multiple of 16; both pointers 16-byte aligned, non-overlapping) from
+ * src_dev to dst_dev with a plain streaming kernel.  Used to scale hardware
+ * byte counters: it reads and writes exactly `bytes` each.
+ */
+mf_status mf_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, mf_stream_t stream);
 
 #ifdef __cplusplus
 }

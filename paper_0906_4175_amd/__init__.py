@@ -22,7 +22,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
+__all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_plan", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
            "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": L.MF_FP64, "fp32_ph64": L.MF_FP32_PH64, "fp32": L.MF_FP32}
@@ -134,6 +134,15 @@ def filter_workspace_bytes(grid: Grid, precision, n_tmpl: int, n_seg: int) -> in
     if nb == 0:
         raise L.MfError(-1, _clib.mf_last_error().decode())
     return nb
+
+
+def filter_plan(grid: Grid, precision="fp32_ph64") -> dict:
+    """The launch plan mf_filter uses for this grid and precision."""
+    arr = (C.c_int32 * 8)()
+    g = grid.c()
+    L.check(_clib.mf_filter_plan(C.byref(g), _prec(precision), arr))
+    keys = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "fused")
+    return dict(zip(keys, [int(x) for x in arr]))
 
 
 def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, precision="fp32_ph64",

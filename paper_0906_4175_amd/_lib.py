@@ -42,7 +42,7 @@ class MfError(RuntimeError):
 EXPORTS = [
     "mf_last_error", "mf_version", "mf_bank_bytes", "mf_filter_workspace_bytes", "mf_psd",
     "mf_spa_bank", "mf_filter", "mf_ifft_workspace_bytes", "mf_ifft", "mf_snr_grad",
-    "mf_timing_enable", "mf_timing_read",
+    "mf_timing_enable", "mf_timing_read", "mf_probe_copy", "mf_filter_plan",
 ]
 
 _lib = None
@@ -82,7 +82,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_timing_enable.restype = C.c_int
     lib.mf_timing_enable.argtypes = [i32]
     lib.mf_timing_read.restype = C.c_int
-    lib.mf_timing_read.argtypes = [P(dbl), P(i64), P(i64), P(dbl), P(i64), P(i64)]
+    lib.mf_timing_read.argtypes = [P(dbl), P(i64), P(i64), P(i64)]
+    lib.mf_filter_plan.restype = C.c_int
+    lib.mf_filter_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
+    lib.mf_probe_copy.restype = C.c_int
+    lib.mf_probe_copy.argtypes = [vp, vp, sz, vp]
     _lib = lib
     return lib
 

@@ -40,153 +40,43 @@ struct Partial64 {
     int32_t cnt;
 };
 
-// Per-(log2 N, precision) shape of the two passes.
-template <int LOG2N, typename T>
-struct Cfg {
-    static constexpr int N1 = 1 << (LOG2N / 2);
-    static constexpr int N2 = 1 << (LOG2N - LOG2N / 2);
-    static constexpr int BUF1 = std::is_same<T, float>::value ? 16384 : 4096;  // LDS elements, pass 1
-    static constexpr int C0 = BUF1 / N1;
-    static constexpr int CMAX = std::is_same<T, float>::value ? 16 : 8;
-    static constexpr int C = C0 < CMAX ? (C0 < 1 ? 1 : C0) : CMAX;
-    static constexpr int NT1R = C * N1 / 16;
-    static constexpr int NT1 = NT1R < 64 ? 64 : (NT1R > 1024 ? 1024 : NT1R);
-    static constexpr int B0 = 4096 / N2;
-    static constexpr int B = B0 > N1 ? N1 : (B0 < 1 ? 1 : B0);
-    static constexpr int NT2R = B * N2 / 16;
-    static constexpr int NT2 = NT2R < 64 ? 64 : (NT2R > 1024 ? 1024 : NT2R);
-};
+// Weight of the input-index digit that stage s of an L-point Stockham
+// transform consumes: L / (span * radix).
+__host__ __device__ constexpr int digit_weight(int L, int s) { return L / (span_before(L, s) * radix_at(L, s)); }
 
-// ---------------------------------------------------------------------------
-// Pass 1
-// ---------------------------------------------------------------------------
-// PH: 0 = FP64 phase, 1 = FP32 phase.  RAW: input is a full N-point spectrum
-// (diagnostic inverse DFT) instead of the template x weight product.
-template <typename T, int PH, bool RAW, int N1, int N2, int C, int NT>
-__global__ void __launch_bounds__(NT) k_pass1(FilterArgs a) {
-    constexpr int64_t N = (int64_t)N1 * N2;
-    constexpr int NS = num_stages(N1);
-    constexpr int LOG2N2 = ilog2(N2);
-    __shared__ cx<T> buf[N1 * C];
-    __shared__ cx<T> t1[N1];  // e^{+2 pi i m / N1}
-    __shared__ cx<T> t2[N2];  // e^{+2 pi i m / N}
+// Stage twiddle tables, one contiguous table per stage s >= 1:
+// e^{+2 pi i k / (span_s R_s)} for k < span_s, so that the lanes of a
+// butterfly row read consecutive entries.
+__host__ __device__ constexpr int tw_offset(int L, int s) {
+    int off = 0;
+    for (int i = 1; i < s; ++i) off += span_before(L, i);
+    return off;
+}
+__host__ __device__ constexpr int tw_total(int L) { return tw_offset(L, num_stages(L)) + 1; }
 
-    const int tid = threadIdx.x;
-    const int k2_0 = blockIdx.x * C;
-    const int64_t ul = blockIdx.y;
-    const int64_t u = a.unit0 + ul;
-
-    for (int m = tid; m < N1; m += NT) t1[m] = root_of_unity((T)m / (T)N1);
-    for (int m = tid; m < N2; m += NT) t2[m] = root_of_unity((T)m / (T)N);
-
-    PhaseCoef coef{};
-    int64_t klo = 0, khi = -1;
-    const cx<T>* w = nullptr;
-    const cx<T>* qin = nullptr;
-    if constexpr (RAW) {
-        qin = (const cx<T>*)a.raw_in + u * N;
-    } else {
-        const int64_t t = u % a.n_tmpl;
-        const int64_t s = u / a.n_tmpl;
-        const mf_bank_entry e = a.bank[t];
-        coef = load_coef(e);
-        klo = e.k_lo;
-        khi = e.k_hi;
-        w = (const cx<T>*)a.wgt + s * (N / 2 + 1);
-        if (blockIdx.x == 0 && tid == 0 && a.keys != nullptr) {
-            a.keys[u] = 0ull;
-            a.counts[u] = 0u;
-        }
+template <typename T, int L>
+__device__ __forceinline__ void fill_stage_twiddles(cx<T>* tw, int tid, int nt) {
+    constexpr int NS = num_stages(L);
+    for (int m = tid; m < tw_total(L); m += nt) {
+        int s = 1;
+#pragma unroll
+        for (int i = 2; i < NS; ++i) s = m >= tw_offset(L, i) ? i : s;
+        const int k = m - tw_offset(L, s);
+        const int M = span_before(L, s) * radix_at(L, s);
+        tw[m] = root_of_unity((T)k / (T)M);
     }
-    __syncthreads();
-
-    cx<T>* inter = (cx<T>*)a.inter + ul * N;
-
-    static_for<0, NS>([&](auto S_) {
-        constexpr int s = decltype(S_)::value;
-        constexpr int R = radix_at(N1, s);
-        constexpr int NSPAN = span_before(N1, s);
-        constexpr int NBF = C * N1 / R;
-        constexpr int BPT = (NBF + NT - 1) / NT;
-        cx<T> v[BPT][R];
-#pragma unroll
-        for (int i = 0; i < BPT; ++i) {
-            const int bf = tid + i * NT;
-            if (NBF % NT == 0 || bf < NBF) {
-                const int c = bf % C;
-                const int j = bf / C;
-                if constexpr (s == 0) {
-                    const int64_t k2 = k2_0 + c;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int64_t k1 = j + r * (N1 / R);
-                        if constexpr (RAW) {
-                            v[i][r] = qin[k1 * N2 + k2];
-                        } else {
-                            v[i][r] = cx<T>{T(0), T(0)};
-                            if (r < R / 2) {  // k1 < N1/2: non-negative frequencies only
-                                const int64_t k = k1 * N2 + k2;
-                                if (k >= klo && k <= khi) {
-                                    cx<T> rotor;
-                                    if constexpr (PH == 0) {
-                                        rotor = spa_rotor_ph64<T>(coef, (double)k);
-                                    } else {
-                                        rotor = spa_rotor_ph32(coef, (float)k);
-                                    }
-                                    v[i][r] = cmul(rotor, w[k]);
-                                }
-                            }
-                        }
-                    }
-                } else {
-                    const int k = j % NSPAN;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * (N1 / R)) * C + c];
-#pragma unroll
-                    for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], t1[(r * k) * (N1 / (NSPAN * R))]);
-                }
-                IDft<R, T>::run(v[i]);
-            }
-        }
-        if constexpr (s == NS - 1) {
-#pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                const int bf = tid + i * NT;
-                if (NBF % NT == 0 || bf < NBF) {
-                    const int c = bf % C;
-                    const int j = bf / C;
-                    const int k2 = k2_0 + c;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int j1 = j + r * NSPAN;
-                        const int m = j1 * k2;  // < N <= 2^22
-                        const cx<T> tw = cmul(t1[m >> LOG2N2], t2[m & (N2 - 1)]);
-                        inter[(int64_t)j1 * N2 + k2] = cmul(v[i][r], tw);
-                    }
-                }
-            }
-        } else {
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                const int bf = tid + i * NT;
-                if (NBF % NT == 0 || bf < NBF) {
-                    const int c = bf % C;
-                    const int j = bf / C;
-                    const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) buf[(idxD + r * NSPAN) * C + c] = v[i][r];
-                }
-            }
-            __syncthreads();
-        }
-    });
 }
 
-// ---------------------------------------------------------------------------
-// Pass 2
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int pad16(int k) { return k + (k >> 4); }
+// p[r] = w^r for r = 0..R-1 by a binary tree of products (depth log2 r).
+template <int R, typename T>
+__device__ __forceinline__ void powers(cx<T> w, cx<T>* p) {
+    p[0] = cx<T>{T(1), T(0)};
+    if constexpr (R > 1) p[1] = w;
+#pragma unroll
+    for (int r = 2; r < R; ++r) p[r] = cmul(p[r / 2], p[r - r / 2]);
+}
+
+__host__ __device__ constexpr int pad16(int k) { return k + (k >> 4); }
 
 __device__ __forceinline__ bool better64(double zz, int j, double bzz, int bj) {
     const bool an = zz != zz, bn = bzz != bzz;
@@ -195,182 +85,437 @@ __device__ __forceinline__ bool better64(double zz, int j, double bzz, int bj) {
     return zz > bzz || (zz == bzz && j < bj);
 }
 
-template <typename T, bool RAW, int N1, int N2, int B, int NT>
-__global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
-    constexpr int64_t N = (int64_t)N1 * N2;
-    constexpr int NS = num_stages(N2);
-    constexpr int PN2 = N2 + N2 / 16;
-    constexpr int NWAVE = NT / 64;
-    constexpr bool F64 = std::is_same<T, double>::value;
-    __shared__ cx<T> buf[B * PN2];
-    __shared__ cx<T> tw2[N2];  // e^{+2 pi i m / N2}
-    __shared__ unsigned long long red_key[NWAVE];
-    __shared__ double red_zz[NWAVE];
-    __shared__ int red_j[NWAVE];
-    __shared__ unsigned int red_cnt[NWAVE];
+// ---------------------------------------------------------------------------
+// Pass 1 tile: C adjacent columns k2 of one unit.
+// PH: 0 = FP64 phase, 1 = FP32 phase.  RAW: input is a full N-point spectrum
+// (diagnostic inverse DFT) instead of the template x weight product.
+// Output: Y[j1][k2] = sum_k1 q[N2 k1 + k2] e^{2 pi i j1 k1 / N1}.
+// ---------------------------------------------------------------------------
+template <typename T, int PH, bool RAW, int N1, int N2, int C, int NT>
+struct Pass1 {
+    static constexpr int64_t N = (int64_t)N1 * N2;
+    static constexpr int NS = num_stages(N1);
+    static constexpr int TW = tw_total(N1);
+    static constexpr size_t SMEM = (size_t)(N1 * C + TW) * sizeof(cx<T>);
 
-    const int tid = threadIdx.x;
-    const int rb = blockIdx.x;
-    const int64_t ul = blockIdx.y;
-    const int64_t u = a.unit0 + ul;
-    const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
+    __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
+        cx<T>* buf = (cx<T>*)smem;
+        cx<T>* tw = buf + N1 * C;
+        const int tid = threadIdx.x;
+        const int k2_0 = tile * C;
+        const int64_t u = a.unit0 + ul;
 
-    for (int m = tid; m < N2; m += NT) tw2[m] = root_of_unity((T)m / (T)N2);
-
-    // peak-search state
-    T thr2 = T(0);
-    double sigma = 1.0;
-    float inv_sigma_f = 1.0f;
-    int slot = -1;
-    if constexpr (!RAW) {
-        const int64_t t = u % a.n_tmpl;
-        const mf_bank_entry e = a.bank[t];
-        sigma = e.sigma;
-        inv_sigma_f = e.inv_sigma;
-        const double th = a.rho_threshold * sigma;
-        thr2 = (T)(th * th);
-        const int64_t pub = t * a.n_seg + u / a.n_tmpl;  // public unit id t * n_seg + s
-        for (int i = 0; i < a.n_series; ++i)
-            if (a.series_units[i] == pub) slot = i;
-    }
-    unsigned long long best_key = 0ull;
-    double best_zz = -1.0;
-    int best_j = 0x7fffffff;
-    unsigned int cnt = 0u;
-    __syncthreads();
-
-    static_for<0, NS>([&](auto S_) {
-        constexpr int s = decltype(S_)::value;
-        constexpr int R = radix_at(N2, s);
-        constexpr int NSPAN = span_before(N2, s);
-        constexpr int NBF = B * N2 / R;
-        constexpr int BPT = (NBF + NT - 1) / NT;
-        constexpr int PER_ROW = N2 / R;
-        cx<T> v[BPT][R];
-#pragma unroll
-        for (int i = 0; i < BPT; ++i) {
-            const int bf = tid + i * NT;
-            if (NBF % NT == 0 || bf < NBF) {
-                const int j = bf % PER_ROW;
-                const int b = bf / PER_ROW;
-                if constexpr (s == 0) {
-                    const int64_t j1 = (int64_t)rb * B + b;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) v[i][r] = inter[j1 * N2 + j + r * PER_ROW];
-                } else {
-                    const int k = j % NSPAN;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) v[i][r] = buf[b * PN2 + pad16(j + r * PER_ROW)];
-#pragma unroll
-                    for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw2[(r * k) * (N2 / (NSPAN * R))]);
-                }
-                IDft<R, T>::run(v[i]);
+        PhaseCoef coef{};
+        int64_t klo = 0, khi = -1;
+        const cx<T>* w = nullptr;
+        const cx<T>* qin = nullptr;
+        if constexpr (RAW) {
+            qin = (const cx<T>*)a.raw_in + u * N;
+        } else {
+            const int64_t t = u % a.n_tmpl;
+            const int64_t s = u / a.n_tmpl;
+            const mf_bank_entry e = a.bank[t];
+            coef = load_coef(e);
+            klo = e.k_lo;
+            khi = e.k_hi;
+            w = (const cx<T>*)a.wgt + s * (N / 2 + 1);
+            if (tile == 0 && tid == 0 && a.keys != nullptr) {
+                a.keys[u] = 0ull;
+                a.counts[u] = 0u;
             }
         }
-        if constexpr (s == NS - 1) {
+        cx<T>* inter = (cx<T>*)a.inter + ul * N;
+
+        static_for<0, NS>([&](auto S_) {
+            constexpr int s = decltype(S_)::value;
+            constexpr int R = radix_at(N1, s);
+            constexpr int NSPAN = span_before(N1, s);
+            constexpr int NBF = C * N1 / R;
+            constexpr int BPT = (NBF + NT - 1) / NT;
+            cx<T> v[BPT][R];
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                const int bf = tid + i * NT;
+                if (NBF % NT == 0 || bf < NBF) {
+                    const int c = bf % C;
+                    const int j = bf / C;
+                    if constexpr (s == 0) {
+                        const int64_t k2 = k2_0 + c;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int64_t k1 = j + r * (N1 / R);
+                            if constexpr (RAW) {
+                                v[i][r] = qin[k1 * N2 + k2];
+                            } else {
+                                v[i][r] = cx<T>{T(0), T(0)};
+                                if (r < R / 2) {  // k1 < N1/2: non-negative frequencies only
+                                    const int64_t k = k1 * N2 + k2;
+                                    if (k >= klo && k <= khi) {
+                                        cx<T> rotor;
+                                        if constexpr (PH == 0) {
+                                            rotor = spa_rotor_ph64<T>(coef, (double)k);
+                                        } else {
+                                            rotor = spa_rotor_ph32(coef, (float)k);
+                                        }
+                                        v[i][r] = cmul(rotor, w[k]);
+                                    }
+                                }
+                            }
+                        }
+                    } else {
+                        const int k = j % NSPAN;
+                        const cx<T>* src = buf + j * C + c;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) v[i][r] = src[r * (N1 / R) * C];
+                        cx<T> p[R];
+                        powers<R>(tw[tw_offset(N1, s) + k], p);
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
+                    }
+                    IDft<R, T>::run(v[i]);
+                }
+            }
+            if constexpr (s == 0) fill_stage_twiddles<T, N1>(tw, tid, NT);
+            if constexpr (s == NS - 1) {
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = tid + i * NT;
+                    if (NBF % NT == 0 || bf < NBF) {
+                        const int c = bf % C;
+                        const int j = bf / C;
+                        cx<T>* dst = inter + (int64_t)j * N2 + k2_0 + c;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) dst[(int64_t)r * NSPAN * N2] = v[i][r];
+                    }
+                }
+            } else {
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = tid + i * NT;
+                    if (NBF % NT == 0 || bf < NBF) {
+                        const int c = bf % C;
+                        const int j = bf / C;
+                        const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
+                        cx<T>* dst = buf + idxD * C + c;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) dst[r * NSPAN * C] = v[i][r];
+                    }
+                }
+                __syncthreads();
+            }
+        });
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Pass 2 tile: B rows j1 of one unit.
+// Row j1: z[j1 + N1 j2] = sum_k2 (Y[j1][k2] t^k2) e^{2 pi i j2 k2 / N2}, t = e^{2 pi i j1 / N}.
+// The four-step factor t^k2 is folded into the stage twiddles: writing k2 in
+// the mixed radix of the stages, stage s multiplies its input r by
+// (w_s t^{weight_s})^r with weight_s = N2 / (span_s R_s), so no separate
+// twiddle pass is needed and the result is exact (not only up to a phase).
+// The last stage squares |z| and reduces (max |z|^2, lowest index, count).
+// ---------------------------------------------------------------------------
+template <typename T, bool RAW, int N1, int N2, int B, int NT>
+struct Pass2 {
+    static constexpr int64_t N = (int64_t)N1 * N2;
+    static constexpr int NS = num_stages(N2);
+    static constexpr int PN2 = pad16(N2);
+    static constexpr int NWAVE = NT / 64;
+    static constexpr int TW = tw_total(N2);
+    static constexpr bool F64 = std::is_same<T, double>::value;
+    static constexpr size_t SMEM =
+        (size_t)(B * PN2 + TW + B * NS) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
+    static_assert(B * NS <= NT, "one thread per (row, stage) factor");
+
+    // LDS element offset of padded index x + r * step when x's padding is known
+    template <int STEP>
+    __device__ static __forceinline__ int off(int x, int r) {
+        if constexpr (STEP % 16 == 0) {
+            return pad16(x) + r * pad16(STEP);
+        } else {
+            return pad16(x + r * STEP);
+        }
+    }
+
+    __device__ static void run(const FilterArgs& a, char* smem, int rb, int64_t ul) {
+        cx<T>* buf = (cx<T>*)smem;
+        cx<T>* tw = buf + B * PN2;
+        cx<T>* trow = tw + TW;  // [B][NS]: t^{weight_s} per row
+        unsigned long long* red_key = (unsigned long long*)(trow + B * NS);
+        double* red_zz = (double*)(red_key + NWAVE);
+        int* red_j = (int*)(red_zz + NWAVE);
+        unsigned int* red_cnt = (unsigned int*)(red_j + NWAVE);
+
+        const int tid = threadIdx.x;
+        const int64_t u = a.unit0 + ul;
+        const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
+
+        if (tid < B * NS) {
+            const int b = tid / NS, st = tid % NS;
+            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st);  // < N
+            trow[b * NS + st] = root_of_unity((T)m / (T)N);
+        }
+
+        T thr2 = T(0);
+        bool count_on = false;
+        const bool full_window = a.j_begin == 0 && a.j_end == N;
+        double sigma = 1.0;
+        float inv_sigma_f = 1.0f;
+        int slot = -1;
+        if constexpr (!RAW) {
+            const int64_t t = u % a.n_tmpl;
+            const mf_bank_entry e = a.bank[t];
+            sigma = e.sigma;
+            inv_sigma_f = e.inv_sigma;
+            const double th = a.rho_threshold * sigma;
+            thr2 = (T)(th * th);
+            count_on = a.rho_threshold < INFINITY;
+            const int64_t pub = t * a.n_seg + u / a.n_tmpl;  // public unit id t * n_seg + s
+            for (int i = 0; i < a.n_series; ++i)
+                if (a.series_units[i] == pub) slot = i;
+        }
+        unsigned long long best_key = 0ull;
+        double best_zz = -1.0;
+        int best_j = 0x7fffffff;
+        unsigned int cnt = 0u;
+        __syncthreads();
+
+        static_for<0, NS>([&](auto S_) {
+            constexpr int s = decltype(S_)::value;
+            constexpr int R = radix_at(N2, s);
+            constexpr int NSPAN = span_before(N2, s);
+            constexpr int NBF = B * N2 / R;
+            constexpr int BPT = (NBF + NT - 1) / NT;
+            constexpr int PER_ROW = N2 / R;
+            cx<T> v[BPT][R];
 #pragma unroll
             for (int i = 0; i < BPT; ++i) {
                 const int bf = tid + i * NT;
                 if (NBF % NT == 0 || bf < NBF) {
                     const int j = bf % PER_ROW;
                     const int b = bf / PER_ROW;
-                    const int j1 = rb * B + b;
+                    cx<T> base = trow[b * NS + s];
+                    if constexpr (s == 0) {
+                        const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int j2 = j + r * NSPAN;
-                        const int jg = j1 + N1 * j2;
+                        for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
+                    } else {
+                        const int k = j % NSPAN;
+                        const cx<T>* src = buf + b * PN2;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
+                        base = cmul(tw[tw_offset(N2, s) + k], base);
+                    }
+                    cx<T> p[R];
+                    powers<R>(base, p);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
+                    IDft<R, T>::run(v[i]);
+                }
+            }
+            if constexpr (s == 0) fill_stage_twiddles<T, N2>(tw, tid, NT);
+            if constexpr (s == NS - 1) {
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = tid + i * NT;
+                    if (NBF % NT == 0 || bf < NBF) {
+                        const int j = bf % PER_ROW;
+                        const int b = bf / PER_ROW;
+                        const int j1 = rb * B + b;
+                        // output r of this butterfly is time sample j1 + N1 (j + r NSPAN): increasing in r
                         if constexpr (RAW) {
-                            ((cx<T>*)a.raw_out)[u * N + jg] = v[i][r];
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+                                ((cx<T>*)a.raw_out)[u * N + j1 + (int64_t)N1 * (j + r * NSPAN)] = v[i][r];
                         } else {
-                            const T zz = norm2(v[i][r]);
+                            T zz[R];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) zz[r] = norm2(v[i][r]);
                             if (slot >= 0) {
-                                if constexpr (F64) {
-                                    ((double*)a.rho)[(int64_t)slot * N + jg] = sqrt(zz) / sigma;
-                                } else {
-                                    ((float*)a.rho)[(int64_t)slot * N + jg] = sqrtf(zz) * inv_sigma_f;
+#pragma unroll
+                                for (int r = 0; r < R; ++r) {
+                                    const int64_t jg = j1 + (int64_t)N1 * (j + r * NSPAN);
+                                    if constexpr (F64) {
+                                        ((double*)a.rho)[(int64_t)slot * N + jg] = sqrt(zz[r]) / sigma;
+                                    } else {
+                                        ((float*)a.rho)[(int64_t)slot * N + jg] = sqrtf(zz[r]) * inv_sigma_f;
+                                    }
                                 }
                             }
-                            if (jg >= a.j_begin && jg < a.j_end) {
-                                cnt += (zz >= thr2) ? 1u : 0u;
+                            if (full_window) {
+                                if (count_on) {
+#pragma unroll
+                                    for (int r = 0; r < R; ++r) cnt += (zz[r] >= thr2) ? 1u : 0u;
+                                }
                                 if constexpr (F64) {
-                                    if (better64(zz, jg, best_zz, best_j)) {
-                                        best_zz = zz;
-                                        best_j = jg;
+#pragma unroll
+                                    for (int r = 0; r < R; ++r) {
+                                        const int jg = j1 + N1 * (j + r * NSPAN);
+                                        if (better64(zz[r], jg, best_zz, best_j)) {
+                                            best_zz = zz[r];
+                                            best_j = jg;
+                                        }
                                     }
                                 } else {
+                                    // integer max of the non-negative float bits (NaN bits exceed +inf,
+                                    // so a NaN propagates), then the lowest r that attains it
+                                    unsigned int mb = __float_as_uint(zz[0]);
+#pragma unroll
+                                    for (int r = 1; r < R; ++r) mb = max(mb, __float_as_uint(zz[r]));
+                                    int rmin = R - 1;
+#pragma unroll
+                                    for (int r = R - 2; r >= 0; --r) rmin = __float_as_uint(zz[r]) == mb ? r : rmin;
+                                    const unsigned int jg = (unsigned int)(j1 + N1 * (j + rmin * NSPAN));
                                     const unsigned long long key =
-                                        ((unsigned long long)__float_as_uint(zz) << 32) |
-                                        (unsigned long long)(0xffffffffu - (unsigned int)jg);
+                                        ((unsigned long long)mb << 32) | (unsigned long long)(0xffffffffu - jg);
                                     best_key = key > best_key ? key : best_key;
+                                }
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < R; ++r) {
+                                    const int jg = j1 + N1 * (j + r * NSPAN);
+                                    if (jg >= a.j_begin && jg < a.j_end) {
+                                        if (count_on) cnt += (zz[r] >= thr2) ? 1u : 0u;
+                                        if constexpr (F64) {
+                                            if (better64(zz[r], jg, best_zz, best_j)) {
+                                                best_zz = zz[r];
+                                                best_j = jg;
+                                            }
+                                        } else {
+                                            const unsigned long long key =
+                                                ((unsigned long long)__float_as_uint(zz[r]) << 32) |
+                                                (unsigned long long)(0xffffffffu - (unsigned int)jg);
+                                            best_key = key > best_key ? key : best_key;
+                                        }
+                                    }
                                 }
                             }
                         }
                     }
                 }
-            }
-        } else {
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                const int bf = tid + i * NT;
-                if (NBF % NT == 0 || bf < NBF) {
-                    const int j = bf % PER_ROW;
-                    const int b = bf / PER_ROW;
-                    const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) buf[b * PN2 + pad16(idxD + r * NSPAN)] = v[i][r];
-                }
-            }
-            __syncthreads();
-        }
-    });
-
-    if constexpr (!RAW) {
-        // work-group reduction: wave shuffles, then one LDS slot per wave
-        const int lane = tid & 63;
-        const int wave = tid >> 6;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            cnt += __shfl_xor(cnt, off, 64);
-            if constexpr (F64) {
-                const double ozz = __shfl_xor(best_zz, off, 64);
-                const int oj = __shfl_xor(best_j, off, 64);
-                if (better64(ozz, oj, best_zz, best_j)) {
-                    best_zz = ozz;
-                    best_j = oj;
-                }
             } else {
-                const unsigned long long o = __shfl_xor(best_key, off, 64);
-                best_key = o > best_key ? o : best_key;
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = tid + i * NT;
+                    if (NBF % NT == 0 || bf < NBF) {
+                        const int j = bf % PER_ROW;
+                        const int b = bf / PER_ROW;
+                        const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
+                        cx<T>* dst = buf + b * PN2;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            if constexpr (NSPAN == 1 && R == 16) {
+                                dst[pad16(idxD) + r] = v[i][r];  // idxD = 16 j: r stays inside the 16-block
+                            } else {
+                                dst[off<NSPAN>(idxD, r)] = v[i][r];
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
             }
-        }
-        if (lane == 0) {
-            red_cnt[wave] = cnt;
-            red_key[wave] = best_key;
-            red_zz[wave] = best_zz;
-            red_j[wave] = best_j;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int w = 1; w < NWAVE; ++w) {
-                cnt += red_cnt[w];
+        });
+
+        if constexpr (!RAW) {
+            // work-group reduction: wave shuffles, then one LDS slot per wave
+            const int lane = tid & 63;
+            const int wave = tid >> 6;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                cnt += __shfl_xor(cnt, o, 64);
                 if constexpr (F64) {
-                    if (better64(red_zz[w], red_j[w], best_zz, best_j)) {
-                        best_zz = red_zz[w];
-                        best_j = red_j[w];
+                    const double ozz = __shfl_xor(best_zz, o, 64);
+                    const int oj = __shfl_xor(best_j, o, 64);
+                    if (better64(ozz, oj, best_zz, best_j)) {
+                        best_zz = ozz;
+                        best_j = oj;
                     }
                 } else {
-                    best_key = red_key[w] > best_key ? red_key[w] : best_key;
+                    const unsigned long long ov = __shfl_xor(best_key, o, 64);
+                    best_key = ov > best_key ? ov : best_key;
                 }
             }
-            if constexpr (F64) {
-                Partial64* part = (Partial64*)a.partials + ul * (N1 / B) + rb;
-                *part = Partial64{best_zz, best_j, (int32_t)cnt};
-            } else {
-                atomicMax(a.keys + u, best_key);
-                if (cnt) atomicAdd(a.counts + u, cnt);
+            if (lane == 0) {
+                red_cnt[wave] = cnt;
+                red_key[wave] = best_key;
+                red_zz[wave] = best_zz;
+                red_j[wave] = best_j;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int wv = 1; wv < NWAVE; ++wv) {
+                    cnt += red_cnt[wv];
+                    if constexpr (F64) {
+                        if (better64(red_zz[wv], red_j[wv], best_zz, best_j)) {
+                            best_zz = red_zz[wv];
+                            best_j = red_j[wv];
+                        }
+                    } else {
+                        best_key = red_key[wv] > best_key ? red_key[wv] : best_key;
+                    }
+                }
+                if constexpr (F64) {
+                    // partials of every unit of the call: [n_units][N1 / B]
+                    Partial64* part = (Partial64*)a.partials + u * (N1 / B) + rb;
+                    *part = Partial64{best_zz, best_j, (int32_t)cnt};
+                } else {
+                    atomicMax(a.keys + u, best_key);
+                    if (cnt) atomicAdd(a.counts + u, cnt);
+                }
             }
         }
+    }
+};
+
+template <size_t A, size_t B>
+struct MaxSz {
+    static constexpr size_t value = A > B ? A : B;
+};
+
+template <typename T, int PH, bool RAW, int N1, int N2, int C, int NT>
+__global__ void __launch_bounds__(NT) k_pass1(FilterArgs a) {
+    using P = Pass1<T, PH, RAW, N1, N2, C, NT>;
+    __shared__ __align__(16) char smem[P::SMEM];
+    P::run(a, smem, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, bool RAW, int N1, int N2, int B, int NT>
+__global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
+    using P = Pass2<T, RAW, N1, N2, B, NT>;
+    __shared__ __align__(16) char smem[P::SMEM];
+    P::run(a, smem, blockIdx.x, blockIdx.y);
+}
+
+// Pipelined step: pass 1 of batch b (a1) and pass 2 of batch b-1 (a2) in one
+// launch.  The two roles touch disjoint intermediates and disjoint units, and
+// their work-groups are interleaved so that every CU mixes the store-bound
+// pass 1 with the arithmetic-bound pass 2.
+template <typename T, int PH, int N1, int N2, int C, int B, int NT>
+__global__ void __launch_bounds__(NT) k_step(FilterArgs a1, FilterArgs a2) {
+    using P1 = Pass1<T, PH, false, N1, N2, C, NT>;
+    using P2 = Pass2<T, false, N1, N2, B, NT>;
+    __shared__ __align__(16) char smem[MaxSz<P1::SMEM, P2::SMEM>::value];
+    constexpr int W1 = N2 / C;  // pass-1 tiles per unit
+    constexpr int W2 = N1 / B;  // pass-2 tiles per unit
+    const int64_t t1 = a1.units * W1, t2 = a2.units * W2;
+    const int64_t m = t1 < t2 ? t1 : t2;
+    const int64_t b = blockIdx.x;
+    bool first;
+    int64_t idx;
+    if (b < 2 * m) {
+        first = (b & 1) == 0;
+        idx = b >> 1;
+    } else {
+        first = t1 > t2;
+        idx = b - m;
+    }
+    if (first) {
+        P1::run(a1, smem, (int)(idx % W1), idx / W1);
+    } else {
+        P2::run(a2, smem, (int)(idx % W2), idx / W2);
     }
 }
 
@@ -392,69 +537,106 @@ __global__ void k_finalize32(const unsigned long long* keys, const unsigned int*
     peaks[t * n_seg + s] = p;
 }
 
-__global__ void k_finalize64(const Partial64* part, int n_part, const mf_bank_entry* bank, int64_t n_tmpl,
-                             int64_t n_seg, int64_t unit0, int64_t units, mf_peak* peaks) {
-    const int64_t ul = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ul >= units) return;
-    const int64_t u = unit0 + ul;
+// One 64-thread work-group per unit: strided scan of the partials, then a
+// shuffle reduction (same order-independent comparison as in pass 2).
+__global__ void __launch_bounds__(64) k_finalize64(const Partial64* part, int n_part, const mf_bank_entry* bank,
+                                                   int64_t n_tmpl, int64_t n_seg, int64_t unit0, mf_peak* peaks) {
+    const int64_t u = unit0 + blockIdx.x;
     const int64_t t = u % n_tmpl, s = u / n_tmpl;
     double bzz = -1.0;
     int bj = 0x7fffffff;
     long long cnt = 0;
-    for (int i = 0; i < n_part; ++i) {
-        const Partial64 p = part[ul * n_part + i];
+    for (int i = threadIdx.x; i < n_part; i += 64) {
+        const Partial64 p = part[u * n_part + i];
         cnt += p.cnt;
         if (better64(p.zz, p.j, bzz, bj)) {
             bzz = p.zz;
             bj = p.j;
         }
     }
-    mf_peak o;
-    o.rho = sqrt(bzz) / bank[t].sigma;
-    o.j = bj;
-    o.n_above = (int32_t)cnt;
-    peaks[t * n_seg + s] = o;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off, 64);
+        const double ozz = __shfl_xor(bzz, off, 64);
+        const int oj = __shfl_xor(bj, off, 64);
+        if (better64(ozz, oj, bzz, bj)) {
+            bzz = ozz;
+            bj = oj;
+        }
+    }
+    if (threadIdx.x == 0) {
+        mf_peak o;
+        o.rho = sqrt(bzz) / bank[t].sigma;
+        o.j = bj;
+        o.n_above = (int32_t)cnt;
+        peaks[t * n_seg + s] = o;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Host side: plans and launchers
+// Host side: instantiated shapes, plans and launchers
 // ---------------------------------------------------------------------------
 size_t cx_bytes(mf_precision prec) { return prec == MF_FP64 ? 16 : 8; }
 
-template <int LOG2N, typename T>
-static void fill_plan(Plan& p) {
-    using K = Cfg<LOG2N, T>;
-    p.log2n = LOG2N;
-    p.n1 = K::N1;
-    p.n2 = K::N2;
-    p.c1 = K::C;
-    p.nt1 = K::NT1;
-    p.b2 = K::B;
-    p.nt2 = K::NT2;
+static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024 : x); }
+
+// Every (precision, N1, N2, C, B) instantiated.  The first entry for each N
+// and precision is its default plan.
+#define MF_SHAPES(X)                                                                                      \
+    X(float, 32, 32, 16, 32) X(float, 32, 64, 16, 32) X(float, 64, 64, 16, 64) X(float, 64, 128, 16, 32)  \
+    X(float, 128, 128, 16, 32) X(float, 128, 256, 16, 16) X(float, 256, 256, 16, 16)                       \
+    X(float, 256, 512, 16, 8) X(float, 512, 512, 16, 8) X(float, 512, 1024, 16, 4)                          \
+    X(float, 256, 4096, 16, 1) X(float, 1024, 2048, 16, 2) X(float, 2048, 2048, 8, 2)                       \
+    X(float, 1024, 1024, 8, 4) X(float, 1024, 1024, 16, 8) X(float, 1024, 1024, 16, 4)                      \
+    X(float, 512, 2048, 16, 2) X(float, 2048, 512, 8, 8)                                                    \
+    X(double, 32, 32, 8, 32) X(double, 32, 64, 8, 32) X(double, 64, 64, 8, 64) X(double, 64, 128, 8, 32)   \
+    X(double, 128, 128, 8, 32) X(double, 128, 256, 8, 16) X(double, 256, 256, 8, 16)                        \
+    X(double, 256, 512, 8, 8) X(double, 512, 512, 8, 8) X(double, 512, 1024, 8, 4)                          \
+    X(double, 512, 2048, 8, 2) X(double, 1024, 2048, 4, 2) X(double, 2048, 2048, 2, 2)                      \
+    X(double, 1024, 1024, 8, 4) X(double, 1024, 1024, 4, 4) X(double, 1024, 1024, 4, 2)
+
+static bool want(mf_precision prec, bool f64) { return (prec == MF_FP64) == f64; }
+
+static void fill(Plan& p, int n1, int n2, int c1, int b2) {
+    p.n1 = n1;
+    p.n2 = n2;
+    p.c1 = c1;
+    p.b2 = b2;
+    p.nt1 = clamp_threads(c1 * n1 / 16);
+    p.nt2 = clamp_threads(b2 * n2 / 16);
+    p.log2n = ilog2((long long)n1 * n2);
+    p.fused = p.nt1 == p.nt2;
 }
 
-#define MF_FOR_EACH_LOG2N(X) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
+bool plan_supported(const Plan& q, mf_precision prec) {
+#define MF_MATCH(T, N1, N2, C, B)                                                                          \
+    if (want(prec, std::is_same<T, double>::value) && q.n1 == N1 && q.n2 == N2 && q.c1 == C && q.b2 == B) \
+        return true;
+    MF_SHAPES(MF_MATCH)
+#undef MF_MATCH
+    return false;
+}
 
 Plan default_plan(int log2n, mf_precision prec) {
     Plan p{};
-    switch (log2n) {
-#define MF_CASE(L)                                   \
-    case L:                                          \
-        if (prec == MF_FP64)                         \
-            fill_plan<L, double>(p);                 \
-        else                                         \
-            fill_plan<L, float>(p);                  \
-        break;
-        MF_FOR_EACH_LOG2N(MF_CASE)
-#undef MF_CASE
-        default:
-            p.log2n = -1;
-            return p;
+    p.log2n = -1;
+    bool found = false;
+#define MF_FIRST(T, N1, N2, C, B)                                                                                 \
+    if (!found && want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n) {           \
+        fill(p, N1, N2, C, B);                                                                                    \
+        found = true;                                                                                             \
     }
-    // keep about 64 MiB of intermediates in flight (fits the 256 MiB last-level cache)
+    MF_SHAPES(MF_FIRST)
+#undef MF_FIRST
+    if (!found) return p;
+    // About 1 GiB of intermediates per batch: long launches amortise the
+    // launch and ramp cost (measured best for N = 2^20 on MI355X).  Separate
+    // pass-1 / pass-2 launches measured slightly faster than the pipelined
+    // step at this batch size, so the step is off by default.
     const size_t bytes_per_unit = ((size_t)1 << log2n) * cx_bytes(prec);
-    size_t u = ((size_t)64 << 20) / bytes_per_unit;
+    size_t u = ((size_t)1 << 30) / bytes_per_unit;
     p.units = (int)(u < 1 ? 1 : (u > 4096 ? 4096 : u));
+    p.fused = false;
     return p;
 }
 
@@ -469,67 +651,86 @@ FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t 
     L.off_w = off;
     off = align256(off + (size_t)n_seg * (size_t)(n / 2 + 1) * cx_bytes(prec));
     L.off_inter = off;
-    off = align256(off + (size_t)L.units_per_batch * (size_t)n * cx_bytes(prec));
+    // the pipelined step keeps two batches of intermediates (written / being read)
+    L.inter_bytes = (size_t)L.units_per_batch * (size_t)n * cx_bytes(prec);
+    off = align256(off + (p.fused ? 2 : 1) * L.inter_bytes);
     L.off_keys = off;
     if (prec != MF_FP64) off = align256(off + (size_t)n_units * 8);
     L.off_counts = off;
     if (prec != MF_FP64) off = align256(off + (size_t)n_units * 4);
     L.off_part = off;
-    if (prec == MF_FP64) off = align256(off + (size_t)L.units_per_batch * (size_t)(p.n1 / p.b2) * sizeof(Partial64));
+    if (prec == MF_FP64) off = align256(off + (size_t)n_units * (size_t)(p.n1 / p.b2) * sizeof(Partial64));
     L.total = off;
     return L;
 }
 
-template <int LOG2N, typename T, int PH, bool RAW>
+template <typename T, int PH, bool RAW, int N1, int N2, int C>
 static hipError_t run_pass1(const FilterArgs& a, hipStream_t s) {
-    using K = Cfg<LOG2N, T>;
-    dim3 grid(K::N2 / K::C, (unsigned)a.units);
-    hipLaunchKernelGGL((k_pass1<T, PH, RAW, K::N1, K::N2, K::C, K::NT1>), grid, dim3(K::NT1), 0, s, a);
+    static_assert(N2 % C == 0 && C <= N2, "pass-1 columns per work-group must tile N2");
+    constexpr int NT = clamp_threads(C * N1 / 16);
+    dim3 grid(N2 / C, (unsigned)a.units);
+    hipLaunchKernelGGL((k_pass1<T, PH, RAW, N1, N2, C, NT>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
-template <int LOG2N, typename T, bool RAW>
+template <typename T, bool RAW, int N1, int N2, int B>
 static hipError_t run_pass2(const FilterArgs& a, hipStream_t s) {
-    using K = Cfg<LOG2N, T>;
-    dim3 grid(K::N1 / K::B, (unsigned)a.units);
-    hipLaunchKernelGGL((k_pass2<T, RAW, K::N1, K::N2, K::B, K::NT2>), grid, dim3(K::NT2), 0, s, a);
+    static_assert(N1 % B == 0 && B <= N1, "pass-2 rows per work-group must tile N1");
+    constexpr int NT = clamp_threads(B * N2 / 16);
+    dim3 grid(N1 / B, (unsigned)a.units);
+    hipLaunchKernelGGL((k_pass2<T, RAW, N1, N2, B, NT>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s) {
-    switch (p.log2n) {
-#define MF_CASE(L)                                                                  \
-    case L:                                                                         \
-        if (prec == MF_FP64)                                                        \
-            return raw ? run_pass1<L, double, 0, true>(a, s) : run_pass1<L, double, 0, false>(a, s); \
-        if (raw) return run_pass1<L, float, 0, true>(a, s);                          \
-        return prec == MF_FP32 ? run_pass1<L, float, 1, false>(a, s) : run_pass1<L, float, 0, false>(a, s);
-        MF_FOR_EACH_LOG2N(MF_CASE)
-#undef MF_CASE
-        default:
-            return hipErrorInvalidValue;
+#define MF_P1(T, N1, N2, C, B)                                                                                  \
+    if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {    \
+        if (raw) return run_pass1<T, 0, true, N1, N2, C>(a, s);                                                \
+        if (std::is_same<T, float>::value && prec == MF_FP32) return run_pass1<float, 1, false, N1, N2, C>(a, s); \
+        return run_pass1<T, 0, false, N1, N2, C>(a, s);                                                        \
     }
+    MF_SHAPES(MF_P1)
+#undef MF_P1
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s) {
-    switch (p.log2n) {
-#define MF_CASE(L)                                                                                 \
-    case L:                                                                                        \
-        if (prec == MF_FP64) return raw ? run_pass2<L, double, true>(a, s) : run_pass2<L, double, false>(a, s); \
-        return raw ? run_pass2<L, float, true>(a, s) : run_pass2<L, float, false>(a, s);
-        MF_FOR_EACH_LOG2N(MF_CASE)
-#undef MF_CASE
-        default:
-            return hipErrorInvalidValue;
+#define MF_P2(T, N1, N2, C, B)                                                                               \
+    if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) \
+        return raw ? run_pass2<T, true, N1, N2, B>(a, s) : run_pass2<T, false, N1, N2, B>(a, s);
+    MF_SHAPES(MF_P2)
+#undef MF_P2
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int PH, int N1, int N2, int C, int B>
+static hipError_t run_step(const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
+    constexpr int NT1 = clamp_threads(C * N1 / 16), NT2 = clamp_threads(B * N2 / 16);
+    if constexpr (NT1 == NT2) {
+        const int64_t blocks = a1.units * (N2 / C) + a2.units * (N1 / B);
+        if (blocks <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_step<T, PH, N1, N2, C, B, NT1>), dim3((unsigned)blocks), dim3(NT1), 0, s, a1, a2);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
+#define MF_ST(T, N1, N2, C, B)                                                                                 \
+    if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {   \
+        if (std::is_same<T, float>::value && prec == MF_FP32) return run_step<float, 1, N1, N2, C, B>(a1, a2, s); \
+        return run_step<T, 0, N1, N2, C, B>(a1, a2, s);                                                       \
+    }
+    MF_SHAPES(MF_ST)
+#undef MF_ST
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize(const Plan& p, mf_precision prec, const FilterArgs& a, mf_peak* peaks, hipStream_t s) {
     if (prec == MF_FP64) {
-        const int threads = 64;
-        const unsigned blocks = (unsigned)((a.units + threads - 1) / threads);
-        hipLaunchKernelGGL(k_finalize64, dim3(blocks), dim3(threads), 0, s, (const Partial64*)a.partials,
-                           p.n1 / p.b2, a.bank, a.n_tmpl, a.n_seg, a.unit0, a.units, peaks);
+        hipLaunchKernelGGL(k_finalize64, dim3((unsigned)a.n_units), dim3(64), 0, s, (const Partial64*)a.partials,
+                           p.n1 / p.b2, a.bank, a.n_tmpl, a.n_seg, (int64_t)0, peaks);
     } else {
         const int threads = 256;
         const unsigned blocks = (unsigned)((a.n_units + threads - 1) / threads);

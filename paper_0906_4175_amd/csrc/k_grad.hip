@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(NT) k_snr_grad(int64_t n, double df, double se
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     for (int64_t k = k_lo + tid; k <= khi; k += NT) {
         const double kd = (double)k;
-        const double u = inv_cbrt_f64(kd);
+        const double u = inv_cbrt_f64_full(kd);
         double ph = series5(g.b, u) + fma(bt, kd, -0.125);
         ph -= rint(ph);
         double sn, cs;

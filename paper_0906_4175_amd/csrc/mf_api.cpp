@@ -6,6 +6,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <string>
 #include <vector>
@@ -20,8 +21,7 @@ thread_local std::string g_err;
 // Measurement hook state (event pairs around sampled pass launches).
 struct TimedLaunch {
     hipEvent_t start, stop;
-    int pass;
-    int64_t units;
+    int64_t units1, units2;  // units of the pass-1 and pass-2 roles in the launch
 };
 struct TimingState {
     int32_t stride = 0;
@@ -121,6 +121,34 @@ void spa_coefficients(double mc, double eta, double df, mf_bank_entry* e) {
 
 }  // namespace
 
+namespace mf {
+
+Plan select_plan(int log2n, mf_precision prec) {
+    Plan p = default_plan(log2n, prec);
+    if (const char* e = getenv("MF_PLAN")) {
+        Plan q = p;
+        int n1 = 0, n2 = 0, c1 = 0, b2 = 0;
+        if (sscanf(e, "%d,%d,%d,%d", &n1, &n2, &c1, &b2) == 4 && (int64_t)n1 * n2 == (int64_t(1) << log2n)) {
+            q.n1 = n1;
+            q.n2 = n2;
+            q.c1 = c1;
+            q.b2 = b2;
+            q.nt1 = c1 * n1 / 16 < 64 ? 64 : (c1 * n1 / 16 > 1024 ? 1024 : c1 * n1 / 16);
+            q.nt2 = b2 * n2 / 16 < 64 ? 64 : (b2 * n2 / 16 > 1024 ? 1024 : b2 * n2 / 16);
+            q.fused = false;
+            if (plan_supported(q, prec)) p = q;
+        }
+    }
+    if (const char* e = getenv("MF_FUSED")) p.fused = e[0] == '1' && p.nt1 == p.nt2;
+    if (const char* e = getenv("MF_UNITS")) {
+        const long v = strtol(e, nullptr, 10);
+        if (v >= 1 && v <= 4096) p.units = (int)v;
+    }
+    return p;
+}
+
+}  // namespace mf
+
 extern "C" {
 
 const char* mf_last_error(void) { return g_err.c_str(); }
@@ -136,8 +164,19 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t
         fail(MF_E_ARG, "bad precision or counts");
         return 0;
     }
-    const mf::Plan p = mf::default_plan(l, prec);
+    const mf::Plan p = mf::select_plan(l, prec);
     return mf::filter_layout(p, prec, grid->n, n_tmpl, n_seg).total;
+}
+
+mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!valid_prec(prec) || !plan) return fail(MF_E_ARG, "bad precision or null plan");
+    const mf::Plan p = mf::select_plan(l, prec);
+    const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, p.fused ? 1 : 0};
+    for (int i = 0; i < 8; ++i) plan[i] = v[i];
+    return ok();
 }
 
 mf_status mf_psd(const mf_grid* grid, double* Sn_dev, double* prefix_dev, mf_stream_t stream) {
@@ -226,10 +265,13 @@ mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, c
     if (o.n_series > 0 && (!o.series_units_dev || !rho_dev))
         return fail(MF_E_ARG, "series requested without series_units_dev / rho_dev");
     if (((uintptr_t)workspace_dev & 255) != 0) return fail(MF_E_ARG, "workspace must be 256-byte aligned");
-    const mf::Plan p = mf::default_plan(l, prec);
-    if (p.log2n != l || (int64_t)p.n1 * p.n2 != n || p.n2 % p.c1 != 0 || p.n1 % p.b2 != 0)
+    const mf::Plan p = mf::select_plan(l, prec);
+    if (p.log2n != l || (int64_t)p.n1 * p.n2 != n || p.n2 % p.c1 != 0 || p.n1 % p.b2 != 0 ||
+        !mf::plan_supported(p, prec))
         return fail(MF_E_UNSUPPORTED, "no plan for n=%lld", (long long)n);
     const mf::FilterLayout L = mf::filter_layout(p, prec, n, n_tmpl, n_seg);
+    if (L.units_per_batch * (int64_t)(p.n2 / p.c1 + p.n1 / p.b2) > (int64_t)0x7fffffff)
+        return fail(MF_E_UNSUPPORTED, "batch too large for one launch");
     if (workspace_bytes < L.total)
         return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
 
@@ -254,39 +296,57 @@ mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, c
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);
     if (e != hipSuccess) return hip_fail(e, "mf_filter weights");
-    for (int64_t u0 = 0; u0 < a.n_units; u0 += L.units_per_batch) {
-        a.unit0 = u0;
-        a.units = (a.n_units - u0) < L.units_per_batch ? (a.n_units - u0) : L.units_per_batch;
+    const int64_t upb = L.units_per_batch;
+    const int64_t nb = (a.n_units + upb - 1) / upb;
+    auto batch = [&](mf::FilterArgs& x, int64_t b, int buf) {
+        x.inter = ws + L.off_inter + (size_t)buf * L.inter_bytes;
+        if (b < 0 || b >= nb) {
+            x.unit0 = 0;
+            x.units = 0;
+        } else {
+            x.unit0 = b * upb;
+            x.units = (a.n_units - x.unit0) < upb ? (a.n_units - x.unit0) : upb;
+        }
+    };
+    // sampled launches get an event pair on the stream (measurement hook)
+    auto timed_launch = [&](const mf::FilterArgs& a1, const mf::FilterArgs& a2, auto&& launch) -> mf_status {
         const bool timed = g_timing.stride > 0 && (g_timing.batch_counter++ % g_timing.stride) == 0;
-        TimedLaunch t1{}, t2{};
+        TimedLaunch t{};
         if (timed) {
-            t1 = TimedLaunch{timing_event(), timing_event(), 1, a.units};
-            t2 = TimedLaunch{timing_event(), timing_event(), 2, a.units};
-            if (!t1.start || !t1.stop || !t2.start || !t2.stop) return fail(MF_E_HIP, "timing event creation failed");
-            hipEventRecord(t1.start, s);
+            t = TimedLaunch{timing_event(), timing_event(), a1.units, a2.units};
+            if (!t.start || !t.stop) return fail(MF_E_HIP, "timing event creation failed");
+            hipEventRecord(t.start, s);
         }
-        e = mf::launch_pass1(p, prec, false, a, s);
-        if (e != hipSuccess) return hip_fail(e, "mf_filter pass1");
+        hipError_t le = launch();
+        if (le != hipSuccess) return hip_fail(le, "mf_filter launch");
         if (timed) {
-            hipEventRecord(t1.stop, s);
-            hipEventRecord(t2.start, s);
+            hipEventRecord(t.stop, s);
+            g_timing.pending.push_back(t);
         }
-        e = mf::launch_pass2(p, prec, false, a, s);
-        if (e != hipSuccess) return hip_fail(e, "mf_filter pass2");
-        if (timed) {
-            hipEventRecord(t2.stop, s);
-            g_timing.pending.push_back(t1);
-            g_timing.pending.push_back(t2);
+        return MF_OK;
+    };
+    if (p.fused) {
+        // step b: pass 1 of batch b into buffer b%2, pass 2 of batch b-1 from buffer (b-1)%2
+        for (int64_t b = 0; b <= nb; ++b) {
+            mf::FilterArgs a1 = a, a2 = a;
+            batch(a1, b, (int)(b & 1));
+            batch(a2, b - 1, (int)((b + 1) & 1));
+            st = timed_launch(a1, a2, [&] { return mf::launch_step(p, prec, a1, a2, s); });
+            if (st != MF_OK) return st;
         }
-        if (prec == MF_FP64) {
-            e = mf::launch_finalize(p, prec, a, peaks_dev, s);
-            if (e != hipSuccess) return hip_fail(e, "mf_filter finalize");
+    } else {
+        for (int64_t b = 0; b < nb; ++b) {
+            mf::FilterArgs a1 = a, none = a;
+            batch(a1, b, 0);
+            batch(none, -1, 0);
+            st = timed_launch(a1, none, [&] { return mf::launch_pass1(p, prec, false, a1, s); });
+            if (st != MF_OK) return st;
+            st = timed_launch(none, a1, [&] { return mf::launch_pass2(p, prec, false, a1, s); });
+            if (st != MF_OK) return st;
         }
     }
-    if (prec != MF_FP64) {
-        e = mf::launch_finalize(p, prec, a, peaks_dev, s);
-        if (e != hipSuccess) return hip_fail(e, "mf_filter finalize");
-    }
+    e = mf::launch_finalize(p, prec, a, peaks_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter finalize");
     return ok();
 }
 
@@ -296,7 +356,7 @@ size_t mf_ifft_workspace_bytes(int64_t n, mf_precision prec, int64_t batch) {
         fail(MF_E_ARG, "bad n/precision/batch");
         return 0;
     }
-    const mf::Plan p = mf::default_plan(l, prec);
+    const mf::Plan p = mf::select_plan(l, prec);
     const int64_t u = batch < p.units ? batch : p.units;
     return (size_t)u * (size_t)n * mf::cx_bytes(prec);
 }
@@ -312,7 +372,7 @@ mf_status mf_ifft(int64_t n, mf_precision prec, const void* q_dev, void* z_dev, 
     if (batch < 1) return fail(MF_E_ARG, "batch=%lld", (long long)batch);
     const size_t need = mf_ifft_workspace_bytes(n, prec, batch);
     if (workspace_bytes < need) return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, need);
-    const mf::Plan p = mf::default_plan(l, prec);
+    const mf::Plan p = mf::select_plan(l, prec);
     const int64_t upb = batch < p.units ? batch : p.units;
     mf::FilterArgs a{};
     a.inter = workspace_dev;
@@ -351,6 +411,15 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
     return ok();
 }
 
+mf_status mf_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, mf_stream_t stream) {
+    if (!src_dev || !dst_dev) return fail(MF_E_ARG, "null pointer argument");
+    if (bytes == 0 || (bytes & 15) != 0 || ((uintptr_t)src_dev & 15) != 0 || ((uintptr_t)dst_dev & 15) != 0)
+        return fail(MF_E_ARG, "bytes and pointers must be non-zero multiples of 16");
+    hipError_t e = mf::launch_copy_probe(src_dev, dst_dev, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mf_probe_copy");
+    return ok();
+}
+
 mf_status mf_timing_enable(int32_t stride) {
     if (stride < 0) return fail(MF_E_ARG, "stride < 0");
     g_timing.stride = stride;
@@ -358,31 +427,28 @@ mf_status mf_timing_enable(int32_t stride) {
     return ok();
 }
 
-mf_status mf_timing_read(double* pass1_ms, int64_t* pass1_launches, int64_t* pass1_units, double* pass2_ms,
-                         int64_t* pass2_launches, int64_t* pass2_units) {
-    if (!pass1_ms || !pass1_launches || !pass1_units || !pass2_ms || !pass2_launches || !pass2_units)
-        return fail(MF_E_ARG, "null pointer argument");
-    double ms[3] = {0, 0, 0};
-    int64_t cnt[3] = {0, 0, 0}, units[3] = {0, 0, 0};
+mf_status mf_timing_read(double* ms, int64_t* launches, int64_t* pass1_units, int64_t* pass2_units) {
+    if (!ms || !launches || !pass1_units || !pass2_units) return fail(MF_E_ARG, "null pointer argument");
+    double tot = 0.0;
+    int64_t cnt = 0, u1 = 0, u2 = 0;
     mf_status st = MF_OK;
     for (const TimedLaunch& t : g_timing.pending) {
         hipError_t e = hipEventSynchronize(t.stop);
         float el = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&el, t.start, t.stop);
         if (e != hipSuccess && st == MF_OK) st = hip_fail(e, "mf_timing_read");
-        ms[t.pass] += el;
-        cnt[t.pass] += 1;
-        units[t.pass] += t.units;
+        tot += el;
+        cnt += 1;
+        u1 += t.units1;
+        u2 += t.units2;
         g_timing.pool.push_back(t.start);
         g_timing.pool.push_back(t.stop);
     }
     g_timing.pending.clear();
-    *pass1_ms = ms[1];
-    *pass1_launches = cnt[1];
-    *pass1_units = units[1];
-    *pass2_ms = ms[2];
-    *pass2_launches = cnt[2];
-    *pass2_units = units[2];
+    *ms = tot;
+    *launches = cnt;
+    *pass1_units = u1;
+    *pass2_units = u2;
     return st == MF_OK ? ok() : st;
 }
 

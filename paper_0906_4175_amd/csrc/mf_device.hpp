@@ -163,35 +163,50 @@ __device__ __forceinline__ cx<double> root_of_unity(double frac) {
 
 // ---------------------------------------------------------------------------
 // Stationary-phase template rotor e^{+i Psi_k} for bin k.
-//   Psi_k / 2 pi = b1 u + b2 u^2 + b3 u^3 + b5 u^5 + c0 + bt k,  u = k^(-1/3)
-// In the FP64-phase modes u comes from an FP32 estimate refined by two
-// Newton steps in FP64 (quadratic convergence from ~1e-7 to full precision),
-// the polynomial is evaluated in FP64 and reduced exactly to [-1/2, 1/2]
-// cycles (subtracting the nearest integer is exact), and only the reduced
-// fraction is rounded to the FFT precision before sin/cos.
+//   Psi_k / 2 pi = b1 u + b2 u^2 + b3 u^3 + b5 u^5 + c0,  u = k^(-1/3)
+// In the FP64-phase modes u is refined to ~1e-13 (below), the polynomial is
+// evaluated in FP64 and reduced exactly to [-1/2, 1/2] cycles (subtracting
+// the nearest integer is exact), and only the reduced fraction is rounded to
+// the FFT precision before sin/cos.
 // ---------------------------------------------------------------------------
+// u = k^{-1/3}: hardware FP32 estimate (relative error ~1e-6), then two
+// Newton steps on g(u) = u^-3 - k, u <- u + u (1 - k u^3) / 3, the first in
+// FP32 and the second in FP64.  Each step squares the relative error (e -> 2e^2),
+// so the FP64 result is accurate to ~1e-13, i.e. ~1e-9 cycles of a phase of
+// 10^3 cycles.
 __device__ __forceinline__ double inv_cbrt_f64(double kd) {
-    float kf = (float)kd;
-    double u = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(kf) * (-1.0f / 3.0f));
-    // Newton on g(u) = u^-3 - k:  u <- u + u (1 - k u^3) / 3
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double u3 = u * u * u;
-        double r = fma(-kd, u3, 1.0);
-        u = fma(u * r, 1.0 / 3.0, u);
-    }
-    return u;
+    const float kf = (float)kd;
+    float uf = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(kf) * (-1.0f / 3.0f));
+    uf = fmaf(uf * fmaf(-kf, uf * uf * uf, 1.0f), 1.0f / 3.0f, uf);
+    const double u = (double)uf;
+    const double r = fma(-kd, u * u * u, 1.0);
+    return fma(u * r, 1.0 / 3.0, u);
+}
+
+// Higher-accuracy variant (two FP64 Newton steps, full double precision) for
+// the gradient kernel, whose phase reaches ~10^6 cycles when t_c is large.
+__device__ __forceinline__ double inv_cbrt_f64_full(double kd) {
+    double u = inv_cbrt_f64(kd);
+    const double r = fma(-kd, u * u * u, 1.0);
+    return fma(u * r, 1.0 / 3.0, u);
 }
 
 struct PhaseCoef {
-    double b1, b2, b3, b5, c0, bt;
+    double b1, b2, b3, b5, c0;
 };
 
+// Bank templates (t_c = 0): Psi/2pi = b1 u + b2 u^2 + b3 u^3 + b5 u^5 + c0.
 __device__ __forceinline__ double spa_cycles_f64(const PhaseCoef& p, double kd) {
-    double u = inv_cbrt_f64(kd);
-    double uu = u * u;
-    double poly = u * fma(u, fma(u, fma(uu, p.b5, p.b3), p.b2), p.b1);
-    return poly + fma(p.bt, kd, p.c0);
+    const double u = inv_cbrt_f64(kd);
+    const double uu = u * u;
+    return fma(u, fma(u, fma(u, fma(uu, p.b5, p.b3), p.b2), p.b1), p.c0);
+}
+
+// e^{2 pi i x} for a reduced fraction |x| <= 1/2 with the hardware sine and
+// cosine, which take their argument in revolutions (max abs error ~1.3e-7 on
+// this range, measured against FP64).
+__device__ __forceinline__ cx<float> rotor_rev(float x) {
+    return {__builtin_amdgcn_cosf(x), __builtin_amdgcn_sinf(x)};
 }
 
 // FP64 phase, rotor in precision T
@@ -199,7 +214,11 @@ template <typename T>
 __device__ __forceinline__ cx<T> spa_rotor_ph64(const PhaseCoef& p, double kd) {
     double ph = spa_cycles_f64(p, kd);
     ph -= rint(ph);
-    return root_of_unity((T)ph);
+    if constexpr (sizeof(T) == 4) {
+        return rotor_rev((float)ph);
+    } else {
+        return root_of_unity(ph);
+    }
 }
 
 // FP32 phase throughout (precision study): u, polynomial and reduction in FP32.
@@ -210,13 +229,13 @@ __device__ __forceinline__ cx<float> spa_rotor_ph32(const PhaseCoef& p, float kf
     u = fmaf(u * fmaf(-kf, u3, 1.0f), 1.0f / 3.0f, u);
     float uu = u * u;
     float poly = u * fmaf(u, fmaf(u, fmaf(uu, (float)p.b5, (float)p.b3), (float)p.b2), (float)p.b1);
-    float ph = poly + fmaf((float)p.bt, kf, (float)p.c0);
+    float ph = poly + (float)p.c0;
     ph -= rintf(ph);
-    return root_of_unity(ph);
+    return rotor_rev(ph);
 }
 
 __device__ __forceinline__ PhaseCoef load_coef(const mf_bank_entry& e) {
-    return PhaseCoef{e.b1, e.b2, e.b3, e.b5, e.c0, 0.0};
+    return PhaseCoef{e.b1, e.b2, e.b3, e.b5, e.c0};
 }
 
 }  // namespace mf

@@ -24,16 +24,20 @@ struct Plan {
     int nt1;         // threads per pass-1 work-group
     int b2;          // rows per pass-2 work-group
     int nt2;         // threads per pass-2 work-group
-    int units;       // (template, segment) units whose intermediate is in flight
+    int units;       // (template, segment) units per batch
+    bool fused;      // pipelined step kernel (pass 1 of batch b with pass 2 of batch b-1)
 };
 
 Plan default_plan(int log2n, mf_precision prec);
+bool plan_supported(const Plan& p, mf_precision prec);
+// default plan, overridden by MF_PLAN="n1,n2,c1,b2" and MF_UNITS="units" when set
+Plan select_plan(int log2n, mf_precision prec);
 
 size_t cx_bytes(mf_precision prec);
 
 // Workspace carve-up of mf_filter.
 struct FilterLayout {
-    size_t off_w, off_inter, off_keys, off_counts, off_part, total;
+    size_t off_w, off_inter, inter_bytes, off_keys, off_counts, off_part, total;
     int64_t units_per_batch;
 };
 FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg);
@@ -44,7 +48,7 @@ struct FilterArgs {
     void* inter;              // [units][n]
     unsigned long long* keys; // [n_units] (FP32 modes)
     unsigned int* counts;     // [n_units] (FP32 modes)
-    void* partials;           // [units][n1/b2] (FP64)
+    void* partials;           // [n_units][n1/b2] (FP64)
     int64_t n_tmpl, n_seg, n_units;
     int64_t unit0, units;     // batch
     int64_t j_begin, j_end;
@@ -59,8 +63,10 @@ struct FilterArgs {
 // Launchers (return hipError_t of the launch)
 hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
 hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
+hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s);
 hipError_t launch_finalize(const Plan& p, mf_precision prec, const FilterArgs& a, mf_peak* peaks, hipStream_t s);
 
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_psd(int64_t n, double fs, double f_low, double f0, int k_lo, double* Sn, hipStream_t s);
 hipError_t launch_prefix(int64_t n, double fs, const double* Sn, double* prefix, hipStream_t s);
 hipError_t launch_weights(int64_t n, double fs, int k_lo, mf_precision prec, const void* stilde, int64_t n_seg,

@@ -1,0 +1,72 @@
+"""Workload driver for hardware-counter runs (rocprofv3 --pmc).
+
+Runs, in one process: the calibration copy kernel over a buffer of known size
+(it reads and writes exactly that many bytes), then mf_filter on a benchmark
+workload for a few steps.  Usage (from the repository root):
+
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o run -- \\
+      python3 paper_0906_4175_amd/profile_run.py --workload 2 --steps 2
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--precision", default="fp32_ph64")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    args = ap.parse_args()
+
+    import torch
+
+    import paper_0906_4175_amd as mf
+    import synth
+    from paper_0906_4175_amd import _lib as L
+
+    dev = torch.device("cuda:0")
+    lib = L.load()
+    nb = args.copy_mib << 20
+    a = torch.empty(nb, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    L.check(lib.mf_probe_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nb, None))
+    torch.cuda.synchronize()
+    del a, b
+
+    wl = synth.WORKLOADS[args.workload]
+    grid = mf.Grid(wl.n, wl.fs, wl.f_low)
+    Sn = mf.psd(grid, device=dev)
+    Sh = Sn.cpu().numpy()
+    k_lo = grid.k_lo
+    rngs = synth.rngs(args.workload, wl.n_seg)
+    segs = [synth.coloured_noise(Sh[k_lo: wl.n // 2], grid.df, k_lo, wl.n // 2 + 1, rngs[i], dtype=np.complex64)
+            for i in range(wl.n_seg)]
+    st = torch.from_numpy(np.stack(segs)).to(dev)
+    if args.precision == "fp64":
+        st = st.to(torch.complex128)
+    if args.workload == 2:
+        mc, eta = synth.bank_mc_eta_grid()
+    else:
+        mc, eta, _, _ = synth.bank_uneven({3: 8192, 5: 32768}[args.workload], synth.rngs(args.workload, 1)[0])
+    bank = mf.spa_bank(grid, mc, eta, Sn, args.precision)
+    ws = torch.empty(mf.filter_workspace_bytes(grid, args.precision, bank.n_tmpl, wl.n_seg), dtype=torch.uint8,
+                     device=dev)
+    for _ in range(args.steps):
+        res = mf.filter(grid, bank, st, Sn, args.precision, workspace=ws)
+    torch.cuda.synchronize()
+    print(f"profile_run done: copy {args.copy_mib} MiB, {args.steps} steps of {wl.name}, "
+          f"max rho {float(res['rho'].max()):.4f}")
+
+
+if __name__ == "__main__":
+    main()

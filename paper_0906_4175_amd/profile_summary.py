@@ -1,0 +1,111 @@
+"""Summarise rocprofv3 output into the short text files kept under profiles/.
+
+  python3 paper_0906_4175_amd/profile_summary.py --stats DIR_KTRACE \\
+      --fetch DIR_FETCH --write DIR_WRITE --workload NAME --copy-mib 1024 --out OUTDIR
+
+--stats: a `rocprofv3 --kernel-trace --stats --output-format csv` directory;
+--fetch / --write: `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+profile_run.py.  The byte counters are scaled by the factor that makes the
+calibration copy kernel read and write exactly --copy-mib MiB.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f) for f in ("k_filter.hip", "mf_device.hpp")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    for key in ("k_pass1", "k_pass2", "k_step", "k_copy_probe", "k_finalize32", "k_finalize64", "k_weights",
+                "k_sigma", "k_psd", "k_spa_synth", "k_snr_grad", "k_prefix"):
+        if key in name:
+            prec = "fp64" if "<double" in name else ("fp32" if "<float" in name else "")
+            return f"{key}_{prec}" if prec else key
+    return name.split("(")[0][:40]
+
+
+def find(d, pattern):
+    hits = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not hits:
+        raise SystemExit(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def counters(d, counter):
+    rows = list(csv.DictReader(open(find(d, "*counter_collection.csv"))))
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        per.setdefault(short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return per
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command-stats", default="")
+    ap.add_argument("--command-fetch", default="")
+    ap.add_argument("--command-write", default="")
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    khash = kernel_hash()
+    if args.stats:
+        rows = list(csv.DictReader(open(find(args.stats, "*kernel_stats.csv"))))
+        lines = [f"# rocprofv3 kernel trace statistics, workload {args.workload}",
+                 f"# command: {args.command_stats}", f"kernel_source_hash: {khash}",
+                 f"{'kernel':<22} {'calls':>7} {'avg_us':>10} {'total_ms':>10} {'pct':>6}"]
+        for r in rows:
+            avg_ns = float(r.get("AverageNs", 0.0))
+            tot_ns = float(r.get("TotalDurationNs", 0.0))
+            lines.append(f"{short(r['Name']):<22} {int(float(r['Calls'])):>7} {avg_ns / 1e3:>10.2f} "
+                         f"{tot_ns / 1e6:>10.3f} {float(r.get('Percentage', 0.0)):>6.2f}")
+        with open(os.path.join(args.out, f"ktrace_{args.workload}.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    if args.fetch and args.write:
+        f = counters(args.fetch, "FETCH_SIZE")
+        w = counters(args.write, "WRITE_SIZE")
+        copy_bytes = args.copy_mib << 20
+        f_copy = statistics.mean(f["k_copy_probe"]) * 1024.0
+        w_copy = statistics.mean(w["k_copy_probe"]) * 1024.0
+        sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
+        for k in sorted(set(f) & set(w)):
+            if not k.startswith(("k_pass1", "k_pass2", "k_step")):
+                continue
+            fb = statistics.mean(f[k]) * 1024.0 * sf
+            wb = statistics.mean(w[k]) * 1024.0 * sw
+            path = os.path.join(args.out, f"traffic_{k}_{args.workload}.txt")
+            with open(path, "w") as fh:
+                fh.write(f"# HBM traffic per dispatch of {k}, workload {args.workload}\n")
+                fh.write(f"# fetch command: {args.command_fetch}\n# write command: {args.command_write}\n")
+                fh.write(f"kernel_source_hash: {khash}\n")
+                fh.write(f"dispatches: {len(f[k])}\n")
+                fh.write(f"fetch_kib_raw: {statistics.mean(f[k]):.1f}\nwrite_kib_raw: {statistics.mean(w[k]):.1f}\n")
+                fh.write(f"copy_calibration: {args.copy_mib} MiB copy read FETCH_SIZE {f_copy / 1024:.1f} KiB, "
+                         f"WRITE_SIZE {w_copy / 1024:.1f} KiB -> scale fetch x{sf:.4f}, write x{sw:.4f}\n")
+                fh.write(f"fetch_bytes_per_launch: {fb:.0f}\nwrite_bytes_per_launch: {wb:.0f}\n")
+                fh.write(f"hbm_bytes_per_launch: {fb + wb:.0f}\n")
+    print("written to", args.out)
+
+
+if __name__ == "__main__":
+    main()
