@@ -128,6 +128,18 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
 mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 
 /*
+ * Tuning support.  mf_plan_candidates writes up to `cap` candidate plans
+ * (8 int32 each, same layout as mf_filter_plan, units = 0) for this N and
+ * precision and returns how many exist (-1 on invalid arguments).
+ * mf_set_plan installs a plan (units in [1, 4096]) for every later call with
+ * this N and precision class (FP64 vs FP32 modes) in the process; NULL
+ * restores the built-in default.  MF_E_UNSUPPORTED for a shape that is not
+ * built.  Thread-safe.
+ */
+int32_t mf_plan_candidates(const mf_grid* grid, mf_precision prec, int32_t* plans, int32_t cap);
+mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan[8]);
+
+/*
  * mf_psd -- Eq. (2) on the one-sided bins (setup call).
  *   Sn_dev     [N/2+1] double, written: S_n(k df) for k_lo <= k <= N/2-1,
  *              +inf at the other bins (DC, below f_low, Nyquist), so that
@@ -214,6 +226,19 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
                       const int32_t* seg_dev, int64_t n, const void* stilde_dev, int64_t n_seg,
                       const double* Sn_dev, mf_precision prec, double* Z_dev, double* rho2_dev,
                       const double* gbar_dev, double* grad_dev, mf_stream_t stream);
+
+/*
+ * mf_template_metric -- phase-maximised template-space metric at theta over
+ * the band [k_lo, khi] (hot call).  With W_k = f_k^(-7/3)/S_k (= |h_k|^2/S_k,
+ * the weight of Eq. (4)) and d_k = dPsi(f_k)/dtheta in radians,
+ *   g_ij = <d_i d_j> - <d_i><d_j>,   <x> = sum_k W_k x_k / sum_k W_k,
+ * so that near a maximum F(theta + delta) ~ F(theta) (1 - g_ij delta_i delta_j).
+ *   theta_dev  [n][3] (M_c [M_sun], eta, t_c [s]);  khi_dev [n] int32 (required).
+ *   metric_dev [n][6] double: (g_mm, g_me, g_mt, g_ee, g_et, g_tt).
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_BAND, MF_E_HIP.
+ */
+mf_status mf_template_metric(const mf_grid* grid, const double* theta_dev, const int32_t* khi_dev, int64_t n,
+                             const double* Sn_dev, double* metric_dev, mf_stream_t stream);
 
 /*
  * Measurement hook (not part of the method).  With stride > 0, mf_filter

@@ -289,6 +289,24 @@ def snr_sq(theta, stilde: np.ndarray, Sn: np.ndarray, n: int, fs: float,
     return float(abs(Z) ** 2 / sig2), complex(Z), np.array(grad)
 
 
+def template_metric(theta, Sn: np.ndarray, n: int, fs: float, k_lo: int, k_hi: int) -> np.ndarray:
+    """Phase-maximised template-space metric g (3x3) at theta over a frozen band.
+
+    With weights W_k = |h_k|^2 / S_k = f_k^(-7/3) / S_k (the integrand of
+    Eq. (4)) and d_k = dPsi_k/dtheta, g_ij = <d_i d_j> - <d_i><d_j>, <x> the
+    W-weighted mean; near a maximum of rho^2, F(theta + delta) ~
+    F(theta) (1 - g_ij delta_i delta_j).
+    """
+    mc, eta, tc = (float(t) for t in theta)
+    f = freqs(n, fs)[k_lo: k_hi + 1]
+    W = spa_amplitude(f) ** 2 / Sn[k_lo: k_hi + 1]
+    _, d_mc, d_eta, d_tc = _spa_phase_and_partials(f, mc, eta, tc)
+    d = np.stack([d_mc, d_eta, d_tc])
+    mean = (d * W).sum(axis=1) / W.sum()
+    second = (d[:, None, :] * d[None, :, :] * W).sum(axis=2) / W.sum()
+    return second - np.outer(mean, mean)
+
+
 def snr_sq_fd_grad(theta, stilde, Sn, n, fs, k_lo, k_hi, rel: float = 1e-6):
     """Central finite differences of F: relative step for M_c and eta, 1e-6 dt for t_c."""
     theta = np.asarray(theta, dtype=np.float64)
@@ -322,5 +340,5 @@ __all__ = [
     "total_mass_from_mc_eta", "f_isco", "band_lo", "band", "spa_phase",
     "spa_amplitude", "spa_template", "quadrature_partner", "sigma_sq",
     "inverse_dft", "filter_z", "filter_z_literal", "snr", "peak", "filter_unit",
-    "snr_sq", "snr_sq_fd_grad", "naive_dft",
+    "snr_sq", "snr_sq_fd_grad", "template_metric", "naive_dft",
 ]

@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -23,7 +24,8 @@ import torch
 from . import _lib as L
 
 __all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_plan", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
-           "PRECISIONS", "version"]
+           "PRECISIONS", "version",
+           "template_metric"]
 
 PRECISIONS = {"fp64": L.MF_FP64, "fp32_ph64": L.MF_FP32_PH64, "fp32": L.MF_FP32}
 SIGMA_MODES = {"fp64": L.MF_SIGMA_FP64, "comp32": L.MF_SIGMA_COMP32}
@@ -145,6 +147,21 @@ def filter_plan(grid: Grid, precision="fp32_ph64") -> dict:
     return dict(zip(keys, [int(x) for x in arr]))
 
 
+_tune_cache_loaded = False
+
+
+def _maybe_load_tune_cache():
+    """Install plans from $MF_TUNE_CACHE once per process (first filter call)."""
+    global _tune_cache_loaded
+    if _tune_cache_loaded:
+        return
+    _tune_cache_loaded = True
+    path = os.environ.get("MF_TUNE_CACHE")
+    if path:
+        from . import tune
+        tune.load_cache(path)
+
+
 def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, precision="fp32_ph64",
            threshold: float = math.inf, window=None, series_units=None, workspace: torch.Tensor | None = None,
            peaks: torch.Tensor | None = None):
@@ -155,6 +172,7 @@ def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, preci
     """
     prec = _prec(precision)
     _require_cuda(stilde, Sn)
+    _maybe_load_tune_cache()
     if stilde.dim() == 1:
         stilde = stilde.unsqueeze(0)
     if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous() or stilde.shape[-1] != grid.n // 2 + 1:
@@ -231,6 +249,20 @@ def snr_sq(grid: Grid, theta: torch.Tensor, seg: torch.Tensor, stilde: torch.Ten
                           _ptr(Sn), prec, _ptr(Z), _ptr(F), _ptr(gbar), _ptr(grad), _stream(dev))
     L.check(st)
     return F, Z, grad
+
+
+def template_metric(grid: Grid, theta: torch.Tensor, Sn: torch.Tensor, khi: torch.Tensor) -> torch.Tensor:
+    """Phase-maximised template metric g [n, 3, 3] at theta over the frozen bands."""
+    _require_cuda(theta, Sn, khi)
+    theta = theta.to(torch.float64).contiguous()
+    khi = khi.to(torch.int32).contiguous()
+    n = int(theta.shape[0])
+    out = torch.empty((n, 6), dtype=torch.float64, device=theta.device)
+    g = grid.c()
+    L.check(_clib.mf_template_metric(C.byref(g), _ptr(theta), _ptr(khi), n, _ptr(Sn), _ptr(out),
+                                      _stream(theta.device)))
+    idx = torch.tensor([[0, 1, 2], [1, 3, 4], [2, 4, 5]], device=theta.device)
+    return out[:, idx]
 
 
 class SnrSq(torch.autograd.Function):

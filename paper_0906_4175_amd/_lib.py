@@ -42,7 +42,8 @@ class MfError(RuntimeError):
 EXPORTS = [
     "mf_last_error", "mf_version", "mf_bank_bytes", "mf_filter_workspace_bytes", "mf_psd",
     "mf_spa_bank", "mf_filter", "mf_ifft_workspace_bytes", "mf_ifft", "mf_snr_grad",
-    "mf_timing_enable", "mf_timing_read", "mf_probe_copy", "mf_filter_plan",
+    "mf_timing_enable", "mf_timing_read", "mf_probe_copy", "mf_filter_plan", "mf_plan_candidates", "mf_set_plan",
+    "mf_template_metric",
 ]
 
 _lib = None
@@ -85,6 +86,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_timing_read.argtypes = [P(dbl), P(i64), P(i64), P(i64)]
     lib.mf_filter_plan.restype = C.c_int
     lib.mf_filter_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
+    lib.mf_plan_candidates.restype = i32
+    lib.mf_plan_candidates.argtypes = [P(MfGrid), C.c_int, P(i32), i32]
+    lib.mf_set_plan.restype = C.c_int
+    lib.mf_set_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
+    lib.mf_template_metric.restype = C.c_int
+    lib.mf_template_metric.argtypes = [P(MfGrid), vp, vp, i64, vp, vp, vp]
     lib.mf_probe_copy.restype = C.c_int
     lib.mf_probe_copy.argtypes = [vp, vp, sz, vp]
     _lib = lib

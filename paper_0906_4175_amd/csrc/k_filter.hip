@@ -608,6 +608,24 @@ static void fill(Plan& p, int n1, int n2, int c1, int b2) {
     p.fused = p.nt1 == p.nt2;
 }
 
+int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
+    int n = 0;
+#define MF_CAND(T, N1, N2, C, B)                                                                        \
+    if (want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n) {            \
+        Plan q{};                                                                                      \
+        fill(q, N1, N2, C, B);                                                                         \
+        q.units = 0;                                                                                   \
+        for (int f = 0; f < (q.nt1 == q.nt2 ? 2 : 1); ++f) {                                           \
+            q.fused = f == 1;                                                                          \
+            if (out && n < cap) out[n] = q;                                                            \
+            ++n;                                                                                       \
+        }                                                                                              \
+    }
+    MF_SHAPES(MF_CAND)
+#undef MF_CAND
+    return n;
+}
+
 bool plan_supported(const Plan& q, mf_precision prec) {
 #define MF_MATCH(T, N1, N2, C, B)                                                                          \
     if (want(prec, std::is_same<T, double>::value) && q.n1 == N1 && q.n2 == N2 && q.c1 == C && q.b2 == B) \

@@ -155,6 +155,77 @@ __global__ void __launch_bounds__(NT) k_snr_grad(int64_t n, double df, double se
     }
 }
 
+// Template-space metric at theta over the frozen band: with weights
+// W_k = f_k^{-7/3} / S_k (= |h_k|^2 / S_k) and d_k = dPsi_k / dtheta (radians),
+//   g_ij = <d_i d_j> - <d_i><d_j>,  <x> = sum_k W_k x_k / sum_k W_k,
+// the phase-maximised mismatch metric: near a maximum of rho^2,
+// F(theta + delta) ~ F(theta) (1 - g_ij delta_i delta_j).  Output per trigger:
+// (g_mm, g_me, g_mt, g_ee, g_et, g_tt).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_metric(int64_t n, double df, int k_lo, const double* theta,
+                                               const int32_t* khi_in, const double* Sn, double* metric) {
+    constexpr int NV = 10;  // W, W d_i (3), W d_i d_j (6)
+    __shared__ double red[NV][NT];
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const double mc = theta[3 * i + 0], eta = theta[3 * i + 1];
+    int64_t khi = khi_in[i];
+    if (khi > n / 2 - 1) khi = n / 2 - 1;
+    const GradCoef g = grad_coef(mc, eta, df);
+    const double amp2 = pow(df, -7.0 / 3.0);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t k = k_lo + tid; k <= khi; k += NT) {
+        const double kd = (double)k;
+        const double u = inv_cbrt_f64_full(kd);
+        const double u7 = u * u * u * u * u * u * u;
+        const double W = amp2 * u7 / Sn[k];  // f^{-7/3} / S
+        const double d0 = 2.0 * M_PI * series5(g.dm, u);
+        const double d1 = 2.0 * M_PI * series5(g.de, u);
+        const double d2 = 2.0 * M_PI * df * kd;
+        acc[0] += W;
+        acc[1] += W * d0;
+        acc[2] += W * d1;
+        acc[3] += W * d2;
+        acc[4] += W * d0 * d0;
+        acc[5] += W * d0 * d1;
+        acc[6] += W * d0 * d2;
+        acc[7] += W * d1 * d1;
+        acc[8] += W * d1 * d2;
+        acc[9] += W * d2 * d2;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) red[v][tid] = acc[v];
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) red[v][tid] += red[v][tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double w = red[0][0];
+        const double m0 = red[1][0] / w, m1 = red[2][0] / w, m2 = red[3][0] / w;
+        double* out = metric + 6 * i;
+        out[0] = red[4][0] / w - m0 * m0;
+        out[1] = red[5][0] / w - m0 * m1;
+        out[2] = red[6][0] / w - m0 * m2;
+        out[3] = red[7][0] / w - m1 * m1;
+        out[4] = red[8][0] / w - m1 * m2;
+        out[5] = red[9][0] / w - m2 * m2;
+    }
+}
+
+hipError_t launch_metric(int64_t n, double fs, int k_lo, const double* theta, const int32_t* khi, int64_t count,
+                         const double* Sn, double* metric, hipStream_t s) {
+    const double df = fs / (double)n;
+    constexpr int NT = 256;
+    hipLaunchKernelGGL((k_metric<NT>), dim3((unsigned)count), dim3(NT), 0, s, n, df, k_lo, theta, khi, Sn, metric);
+    return hipGetLastError();
+}
+
 hipError_t launch_snr_grad(int64_t n, double fs, int k_lo, mf_precision prec, const double* theta,
                            const int32_t* khi, const int32_t* seg, int64_t count, const void* stilde,
                            int64_t n_seg, const double* Sn, double* Z, double* rho2, const double* gbar, double* grad,

@@ -8,7 +8,10 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mf.h"
@@ -123,8 +126,17 @@ void spa_coefficients(double mc, double eta, double df, mf_bank_entry* e) {
 
 namespace mf {
 
+// Plans installed by mf_set_plan (the tuner), keyed by (log2 N, FP64 or not).
+std::mutex g_plan_mu;
+std::map<std::pair<int, bool>, Plan> g_plans;
+
 Plan select_plan(int log2n, mf_precision prec) {
     Plan p = default_plan(log2n, prec);
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find({log2n, prec == MF_FP64});
+        if (it != g_plans.end()) p = it->second;
+    }
     if (const char* e = getenv("MF_PLAN")) {
         Plan q = p;
         int n1 = 0, n2 = 0, c1 = 0, b2 = 0;
@@ -176,6 +188,51 @@ mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]
     const mf::Plan p = mf::select_plan(l, prec);
     const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, p.fused ? 1 : 0};
     for (int i = 0; i < 8; ++i) plan[i] = v[i];
+    return ok();
+}
+
+int32_t mf_plan_candidates(const mf_grid* grid, mf_precision prec, int32_t* plans, int32_t cap) {
+    int l, klo;
+    if (check_grid(grid, &l, &klo) != MF_OK) return -1;
+    if (!valid_prec(prec) || cap < 0 || (cap > 0 && !plans)) {
+        fail(MF_E_ARG, "bad precision or output buffer");
+        return -1;
+    }
+    std::vector<mf::Plan> v((size_t)(cap > 0 ? cap : 0));
+    const int n = mf::plan_candidates(l, prec, v.data(), cap);
+    for (int i = 0; i < n && i < cap; ++i) {
+        const mf::Plan& p = v[(size_t)i];
+        const int32_t row[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, 0, p.fused ? 1 : 0};
+        for (int k = 0; k < 8; ++k) plans[8 * i + k] = row[k];
+    }
+    ok();
+    return n;
+}
+
+mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan[8]) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    std::lock_guard<std::mutex> lk(mf::g_plan_mu);
+    if (!plan) {
+        mf::g_plans.erase({l, prec == MF_FP64});
+        return ok();
+    }
+    mf::Plan q = mf::default_plan(l, prec);
+    q.n1 = plan[0];
+    q.n2 = plan[1];
+    q.c1 = plan[2];
+    q.b2 = plan[3];
+    q.nt1 = q.c1 * q.n1 / 16 < 64 ? 64 : (q.c1 * q.n1 / 16 > 1024 ? 1024 : q.c1 * q.n1 / 16);
+    q.nt2 = q.b2 * q.n2 / 16 < 64 ? 64 : (q.b2 * q.n2 / 16 > 1024 ? 1024 : q.b2 * q.n2 / 16);
+    q.units = plan[6];
+    q.fused = plan[7] != 0;
+    if ((int64_t)q.n1 * q.n2 != grid->n || !mf::plan_supported(q, prec))
+        return fail(MF_E_UNSUPPORTED, "plan %dx%d c=%d b=%d is not built for this N/precision", q.n1, q.n2, q.c1, q.b2);
+    if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
+    if (q.fused && q.nt1 != q.nt2) return fail(MF_E_UNSUPPORTED, "pipelined step needs equal work-group sizes");
+    mf::g_plans[{l, prec == MF_FP64}] = q;
     return ok();
 }
 
@@ -408,6 +465,19 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
     hipError_t e = mf::launch_snr_grad(grid->n, grid->fs, klo, prec, theta_dev, khi_dev, seg_dev, n, stilde_dev, n_seg, Sn_dev,
                                        Z_dev, rho2_dev, gbar_dev, grad_dev, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "mf_snr_grad");
+    return ok();
+}
+
+mf_status mf_template_metric(const mf_grid* grid, const double* theta_dev, const int32_t* khi_dev, int64_t n,
+                             const double* Sn_dev, double* metric_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!theta_dev || !khi_dev || !Sn_dev || !metric_dev) return fail(MF_E_ARG, "null pointer argument");
+    if (n < 1 || n > (int64_t(1) << 31) - 1) return fail(MF_E_ARG, "n=%lld", (long long)n);
+    hipError_t e = mf::launch_metric(grid->n, grid->fs, klo, theta_dev, khi_dev, n, Sn_dev, metric_dev,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mf_template_metric");
     return ok();
 }
 

@@ -30,6 +30,8 @@ struct Plan {
 
 Plan default_plan(int log2n, mf_precision prec);
 bool plan_supported(const Plan& p, mf_precision prec);
+// instantiated shapes for this N and precision (units = 0); returns the count
+int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap);
 // default plan, overridden by MF_PLAN="n1,n2,c1,b2" and MF_UNITS="units" when set
 Plan select_plan(int log2n, mf_precision prec);
 
@@ -75,6 +77,8 @@ hipError_t launch_sigma(int64_t n, double fs, mf_sigma_mode mode, const double* 
                         int64_t n_tmpl, hipStream_t s);
 hipError_t launch_spa_synth(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
                             void* htilde, hipStream_t s);
+hipError_t launch_metric(int64_t n, double fs, int k_lo, const double* theta, const int32_t* khi, int64_t count,
+                         const double* Sn, double* metric, hipStream_t s);
 hipError_t launch_snr_grad(int64_t n, double fs, int k_lo, mf_precision prec, const double* theta,
                            const int32_t* khi, const int32_t* seg, int64_t count, const void* stilde,
                            int64_t n_seg, const double* Sn, double* Z, double* rho2, const double* gbar, double* grad,

@@ -127,3 +127,54 @@ def test_ifft_and_grad_validation(lib):
                            C.c_void_p(256), C.c_void_p(256), None, None, None) == -1
     assert lib.mf_snr_grad(C.byref(g), C.c_void_p(256), None, C.c_void_p(256), 1, C.c_void_p(256), 1,
                            C.c_void_p(256), 1, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256), None, None) == -1
+
+
+def test_plan_candidates_and_set_plan_validation(lib):
+    g = _grid()
+    n = lib.mf_plan_candidates(C.byref(g), 1, None, 0)
+    assert n >= 4
+    buf = (C.c_int32 * (8 * n))()
+    assert lib.mf_plan_candidates(C.byref(g), 1, buf, n) == n
+    shapes = {tuple(buf[8 * i: 8 * i + 4]) for i in range(n)}
+    assert (256, 4096, 16, 1) in shapes
+    for i in range(n):
+        assert buf[8 * i] * buf[8 * i + 1] == 1 << 20
+    bad = (C.c_int32 * 8)(512, 512, 16, 8, 256, 256, 8, 0)  # wrong N
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 0, 0)  # units 0
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -1
+    bad = (C.c_int32 * 8)(1024, 1024, 8, 4, 512, 256, 8, 1)  # fused with unequal work-groups
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
+    good = (C.c_int32 * 8)(1024, 1024, 8, 4, 512, 256, 16, 0)
+    assert lib.mf_set_plan(C.byref(g), 1, good) == 0
+    out = (C.c_int32 * 8)()
+    assert lib.mf_filter_plan(C.byref(g), 1, out) == 0
+    assert list(out)[:4] == [1024, 1024, 8, 4] and out[6] == 16
+    assert lib.mf_set_plan(C.byref(g), 1, None) == 0
+    assert lib.mf_filter_plan(C.byref(g), 1, out) == 0
+    assert list(out)[:4] == [256, 4096, 16, 1]
+
+
+def test_tune_cache_corrupt_and_foreign(tmp_path):
+    import warnings
+    from paper_0906_4175_amd import tune
+    p = tmp_path / "cache.json"
+    p.write_text("{not json")
+    with warnings.catch_warnings(record=True) as w:
+        warnings.simplefilter("always")
+        assert tune.load_cache(str(p), arch="gfx950") == 0
+        assert any("ignored" in str(x.message) for x in w)
+    # a well-formed cache for another architecture installs nothing
+    tune.save_cache(str(p), "gfx942", 1 << 20, 1, {k: 1 for k in tune.PLAN_KEYS})
+    assert tune.load_cache(str(p), arch="gfx950") == 0
+    # a valid entry for this architecture is installed, a bad one is skipped
+    plan = dict(n1=1024, n2=1024, cols_per_wg=8, rows_per_wg=4, threads_pass1=512, threads_pass2=256,
+                units_per_batch=32, fused=0)
+    tune.save_cache(str(p), "gfx950", 1 << 20, 1, plan, 1.0)
+    tune.save_cache(str(p), "gfx950", 1 << 16, 1, dict(plan, n1=7), 1.0)
+    with warnings.catch_warnings(record=True):
+        warnings.simplefilter("always")
+        assert tune.load_cache(str(p), arch="gfx950") == 1
+    assert tune.current_plan(1 << 20, 1)["units_per_batch"] == 32
+    tune.set_plan(1 << 20, 1, None)
+    assert tune.current_plan(1 << 20, 1)["n1"] == 256

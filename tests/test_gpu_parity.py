@@ -376,3 +376,130 @@ def test_batching_and_fusion_bitwise_invariant(mf, prec):
         for i in range(2):  # injected units (rho >= 8): same sample under either split, as the oracle
             o = _oracle_unit(n, fs, mc[i], eta[i], S[i], D.segment(n, fs, 0, noise=False)[1])
             assert int(other["j"][i, i]) == int(ref["j"][i, i]) == o["j"]
+
+
+# ---------------------------------------------------------------------------
+# HIP graph capture and the tuner
+# ---------------------------------------------------------------------------
+def test_filter_graph_capture_replays_match_eager(mf):
+    """mf_filter allocates nothing and never synchronises, so it can be captured."""
+    print("[graph]", flush=True)
+    n, fs = 1 << 16, 2048.0
+    s, _ = D.segment(n, fs, 321, [dict(m1=1.3, m2=1.2, snr=11.0, j0=777, phi0=0.2)])
+    s2, _ = D.segment(n, fs, 322)
+    mc, eta = synth.bank_small_grid()
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
+    st = torch.from_numpy(np.stack([s, s2])).to(_dev())
+    ws = torch.empty(mf.filter_workspace_bytes(g, "fp32_ph64", bank.n_tmpl, 2), dtype=torch.uint8, device=_dev())
+    peaks = torch.zeros(2 * bank.n_tmpl * 2, dtype=torch.float64, device=_dev())
+    eager = mf.filter(g, bank, st, Sn, "fp32_ph64", threshold=4.0, workspace=ws, peaks=peaks)
+    eager = {k: eager[k].clone() for k in ("rho", "j", "n_above")}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        mf.filter(g, bank, st, Sn, "fp32_ph64", threshold=4.0, workspace=ws, peaks=peaks)  # warm on side stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            res = mf.filter(g, bank, st, Sn, "fp32_ph64", threshold=4.0, workspace=ws, peaks=peaks)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        peaks.fill_(-1.0)           # eager work between replays
+        ws.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ("rho", "j", "n_above"):
+            assert torch.equal(res[k], eager[k]), (rep, k)
+
+
+def test_tuner_picks_and_caches_a_plan(mf, tmp_path):
+    print("[tune]", flush=True)
+    from paper_0906_4175_amd import tune
+    n, fs = 1 << 14, 1024.0
+    s, _ = D.segment(n, fs, 55, [dict(m1=2.0, m2=1.5, snr=12.0, j0=999, phi0=1.0)])
+    mc, eta = synth.mc_eta([2.0, 1.2, 5.0, 1.0, 3.0, 8.0], [1.5, 1.1, 1.0, 1.0, 2.5, 6.0])
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
+    st = torch.from_numpy(s[None]).to(_dev())
+    ref = mf.filter(g, bank, st, Sn, "fp32_ph64")
+    cache = str(tmp_path / "tune.json")
+    out = tune.tune(g, bank, st, Sn, "fp32_ph64", units=(2, 6), steps=2, cache=cache)
+    assert len(out["table"]) >= 2
+    assert tune.current_plan(n, 1)["n1"] == out["best"]["n1"]
+    got = mf.filter(g, bank, st, Sn, "fp32_ph64")
+    assert torch.allclose(got["rho"], ref["rho"], rtol=2e-5)
+    assert int(got["j"][0, 0]) == int(ref["j"][0, 0])
+    tune.set_plan(n, 1, None)
+    assert tune.load_cache(cache) == 1
+    assert tune.current_plan(n, 1) == out["best"]
+    tune.set_plan(n, 1, None)
+
+
+def test_refinement_climbs_to_the_injection(mf):
+    """Bank-like triggers (2-8% mismatch) near an injection: the metric-Newton ascent
+    driven by the forward / adjoint / metric kernels raises rho^2 to the peak,
+    every evaluated F matches the oracle, and the adjoint matches finite differences."""
+    print("[refine]", flush=True)
+    from paper_0906_4175_amd import refine as R
+    n, fs = 1 << 16, 2048.0
+    m1, m2, j0 = 1.5, 1.3, 30000
+    s, Sn_ref = D.segment(n, fs, 77, [dict(m1=m1, m2=m2, snr=20.0, j0=j0, phi0=0.4)])
+    mc0, eta0 = map(float, synth.mc_eta(m1, m2))
+    k_lo, k_hi = O.band(n, fs, 40.0, mc0, eta0)
+    Gm = O.template_metric((mc0, eta0, j0 / fs), Sn_ref, n, fs, k_lo, k_hi)
+    rng = np.random.default_rng(3)
+    starts = []
+    for mm in (0.03, 0.05, 0.06, 0.04, 0.05, 0.08, 0.02, 0.07):
+        v = rng.standard_normal(3)
+        v *= np.sqrt(mm / (v @ Gm @ v))
+        t = np.array([mc0, eta0, j0 / fs]) + v
+        t[1] = min(t[1], 0.2499)
+        starts.append(t)
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    st = torch.from_numpy(s[None]).to(_dev())
+    theta0 = torch.tensor(np.array(starts), dtype=torch.float64, device=_dev())
+    m = theta0.shape[0]
+    seg = torch.zeros(m, dtype=torch.int32, device=_dev())
+    khi = torch.full((m,), k_hi, dtype=torch.int32, device=_dev())
+    F0, _ = R.rho2_and_grad(g, theta0, seg, st, Sn, khi)
+    theta, F, evals = R.refine(g, theta0, seg, st, Sn, khi, steps=10)
+    assert bool((F >= F0).all())
+    F_inj = O.snr_sq((mc0, eta0, j0 / fs), s.astype(np.complex128), Sn_ref, n, fs, k_lo, k_hi)[0]
+    final = []
+    for i in range(m):
+        Fo = O.snr_sq(theta[i].cpu().numpy(), s.astype(np.complex128), Sn_ref, n, fs, k_lo, k_hi)[0]
+        assert float(F[i]) == pytest.approx(Fo, rel=1e-6)
+        final.append(Fo / F_inj)
+    print("  final F / F(injection):", np.round(final, 4))
+    assert np.median(final) > 0.995
+    _, ga = R.rho2_and_grad(g, theta0, seg, st, Sn, khi)
+    fd = R.finite_difference_grad(g, theta0, seg, st, Sn, khi)
+    Dm = torch.tensor([mc0 * 1e-3, 1e-3, 1e-4], dtype=torch.float64, device=_dev())
+    err = ((Dm * (ga - fd)).norm(dim=1) / (Dm * fd).norm(dim=1)).max()
+    assert float(err) < 1e-3
+
+
+def test_template_metric_matches_oracle(mf):
+    print("[metric]", flush=True)
+    n, fs = 1 << 20, 4096.0
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    Sn_ref = O.psd_bins(n, fs, 40.0)
+    pairs = [(1.4, 1.4), (3.0, 1.0), (12.0, 2.5), (30.0, 4.0)]
+    th, kh = [], []
+    for m1, m2 in pairs:
+        mc, eta = map(float, synth.mc_eta(m1, m2))
+        th.append([mc, eta, 17.3])
+        kh.append(O.band(n, fs, 40.0, mc, eta)[1])
+    theta = torch.tensor(th, dtype=torch.float64, device=_dev())
+    khi = torch.tensor(kh, dtype=torch.int32, device=_dev())
+    G = mf.template_metric(g, theta, Sn, khi).cpu().numpy()
+    for i in range(len(pairs)):
+        ref = O.template_metric(th[i], Sn_ref, n, fs, 40 * 256, kh[i])
+        scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+        assert np.max(np.abs(G[i] - ref) / scale) < 1e-9, pairs[i]

@@ -410,3 +410,18 @@ def test_snr_sq_equals_filter_output_at_sample_time():
     F, Z, _ = O.snr_sq((mc, eta, j * g["dt"]), s, Sn, n, fs, k_lo, k_hi)
     assert Z == pytest.approx(complex(z[j]), rel=1e-10)
     assert F == pytest.approx(abs(z[j]) ** 2 / sig2, rel=1e-10)
+
+
+def test_template_metric_predicts_the_quadratic_falloff():
+    """Noiseless injection: 1 - F(theta*+delta)/F* = delta^T g delta + O(delta^3),
+    checked against direct evaluations of F along several directions."""
+    n, fs, mc, eta, t0, s, Sn, k_lo, k_hi = _grad_case(noise=False)
+    g = O.template_metric((mc, eta, t0), Sn, n, fs, k_lo, k_hi)
+    assert np.all(np.linalg.eigvalsh(g) > 0)
+    Fs = O.snr_sq((mc, eta, t0), s, Sn, n, fs, k_lo, k_hi)[0]
+    scales = np.array([mc * 2e-5, 2e-5, 2e-6])
+    for direction in ([1, 0, 0], [0, 1, 0], [0, 0, 1], [1, -1, 0], [1, 1, 1]):
+        dlt = np.array(direction, float) * scales
+        F = O.snr_sq((mc + dlt[0], eta + dlt[1], t0 + dlt[2]), s, Sn, n, fs, k_lo, k_hi)[0]
+        pred = dlt @ g @ dlt
+        assert 1.0 - F / Fs == pytest.approx(pred, rel=2e-2), direction
