@@ -228,6 +228,62 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
                       const double* gbar_dev, double* grad_dev, mf_stream_t stream);
 
 /*
+ * mf_filter_chisq_workspace_bytes -- device workspace mf_filter_chisq needs:
+ * the weighted data, the band table, and per batch of units the template x
+ * weight product [N/2] and one intermediate [N], plus peak partials.  0 for
+ * invalid arguments (no band-mode plan, p_bands outside [2, 64]).
+ */
+size_t mf_filter_chisq_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl,
+                                       int64_t n_seg, int32_t p_bands);
+
+/*
+ * mf_filter_chisq -- the matched filter of mf_filter with the chi^2
+ * time-frequency veto of Eq. (5) (Sec. 1.2) evaluated at EVERY time sample
+ * (hot call: asynchronous, no allocation, no synchronisation).  The
+ * template's band [k_lo, k_hi] is split into p_bands contiguous bands with
+ * equal shares of sigma^2 (a bin belongs to the band in which the sum of
+ * f^(-7/3)/S over the bins before it falls); z_l(t) is Eq. (1) restricted to
+ * band l and
+ *   chi^2(t) = p / sigma^2 sum_l |z_l(t) - z(t)/p|^2,  z = sum_l z_l.
+ *   Arguments as for mf_filter, plus:
+ *   prefix_dev     the prefix array written by mf_psd.
+ *   p_bands        2 <= p <= 64.
+ *   workspace      >= mf_filter_chisq_workspace_bytes(...), 256-byte aligned.
+ *   peaks_dev      [n_tmpl][n_seg]: peak of rho = |z|/sigma (lowest index on
+ *                  ties), threshold count, as mf_filter.
+ *   chisq_dev      [n_tmpl][n_seg] double: chi^2 at each peak, written.
+ *   rho_dev, chisq_series_dev  nullable; with opts->n_series > 0 both receive
+ *                  [n_series][N] series (float for the FP32 modes, double for
+ *                  MF_FP64) for the listed units.
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_WORKSPACE, MF_E_UNSUPPORTED, MF_E_HIP.
+ */
+mf_status mf_filter_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
+                          const void* stilde_dev, int64_t n_seg, const double* Sn_dev,
+                          const double* prefix_dev, mf_precision prec, int32_t p_bands,
+                          const mf_filter_opts* opts, void* workspace_dev, size_t workspace_bytes,
+                          mf_peak* peaks_dev, double* chisq_dev, void* rho_dev,
+                          void* chisq_series_dev, mf_stream_t stream);
+
+/*
+ * mf_chisq -- the chi^2 veto of Eq. (5) (Sec. 1.2) at each unit's peak sample
+ * (hot call).  The template's band [k_lo, k_hi] is split into p_bands
+ * contiguous bands with equal shares of sigma^2 (a bin belongs to the band in
+ * which the sum of f^(-7/3)/S over the bins before it falls), z_l(t) is Eq. (1)
+ * restricted to band l, and
+ *   chi^2(t) = p / sigma^2 sum_l |z_l(t) - z(t)/p|^2 ,
+ * evaluated at t = peaks_dev[u].j * dt for every unit u = t*n_seg + s.
+ *   bank_dev, stilde_dev, Sn_dev as for mf_filter; prefix_dev is the prefix
+ *   array written by mf_psd; peaks_dev [n_tmpl][n_seg] from mf_filter.
+ *   chisq_dev [n_tmpl][n_seg] double, written (NaN for an invalid peak index).
+ *   rho_dev   nullable [n_tmpl][n_seg] double: |z(j)|/sigma recomputed in FP64.
+ *   2 <= p_bands <= 64.
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_BAND, MF_E_HIP.
+ */
+mf_status mf_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev, int64_t n_seg,
+                   const double* Sn_dev, const double* prefix_dev, mf_precision prec, int32_t p_bands,
+                   const mf_peak* peaks_dev, double* chisq_dev, double* rho_dev, mf_stream_t stream);
+
+/*
  * mf_template_metric -- phase-maximised template-space metric at theta over
  * the band [k_lo, khi] (hot call).  With W_k = f_k^(-7/3)/S_k (= |h_k|^2/S_k,
  * the weight of Eq. (4)) and d_k = dPsi(f_k)/dtheta in radians,

@@ -43,6 +43,9 @@ R13 Gradient of rho^2 w.r.t. (M_c, eta, t_c): the band K is frozen at the
     starting template; F(theta) = |Z(theta)|^2 / sigma^2 with
     Z = 4 df sum_K a_k exp(+i Psi_k(theta)) s_k / S_k, which is z(t) at the
     continuous time t = t_c.
+R16 chi^2 bands (Eq. (5), Sec. 1.2): p contiguous bands of the template's
+    band with equal shares of sigma^2; a bin belongs to the band in which the
+    W-sum of the bins before it falls (W_k = f_k^(-7/3) / S_k).
 """
 from __future__ import annotations
 
@@ -238,6 +241,48 @@ def filter_unit(n: int, fs: float, f_low: float, mc: float, eta: float,
 
 
 # ---------------------------------------------------------------------------
+# Eq. (5): chi^2 time-frequency veto (Sec. 1.2)
+# ---------------------------------------------------------------------------
+def chisq_band_edges(Sn: np.ndarray, n: int, fs: float, k_lo: int, k_hi: int, p: int) -> np.ndarray:
+    """Edges e_0 = k_lo < ... < e_p = k_hi + 1 of p bands that contribute equally to sigma^2.
+
+    Reading R16: with W_k = f_k^(-7/3) / S_k (the integrand of Eq. (4)) and the
+    sum of W over the bins before k, bin k belongs to the band in which that
+    sum falls: e_l = min{k : sum_{k_lo <= k' < k} W_k' >= l / p * sum_band W}.
+    """
+    f = freqs(n, fs)[k_lo: k_hi + 1]
+    W = f ** (-7.0 / 3.0) / Sn[k_lo: k_hi + 1]
+    before = np.concatenate([[0.0], np.cumsum(W)[:-1]])
+    total = float(np.sum(W))
+    edges = [k_lo]
+    for l in range(1, p):
+        hit = np.nonzero(before >= l / p * total)[0]
+        # no bin starts at or past this share: band l and those above are empty
+        edges.append(k_lo + int(hit[0]) if hit.size else k_hi + 1)
+    edges.append(k_hi + 1)
+    return np.array(edges, dtype=np.int64)
+
+
+def chisq_series(stilde: np.ndarray, Sn: np.ndarray, htilde: np.ndarray, n: int, fs: float, k_lo: int, k_hi: int,
+                 p: int = 16):
+    """chi^2(t) = p / sigma^2 sum_l |z_l(t) - z(t)/p|^2 over all N lags (Eq. (5)).
+
+    z_l is Eq. (1) restricted to band l; returns (chi2 [N], z_l [p, N]).
+    """
+    g = grid(n, fs)
+    edges = chisq_band_edges(Sn, n, fs, k_lo, k_hi, p)
+    sig2 = sigma_sq(htilde, Sn, g["df"])
+    zl = np.empty((p, n), dtype=np.complex128)
+    for l in range(p):
+        hb = np.zeros_like(htilde)
+        hb[edges[l]: edges[l + 1]] = htilde[edges[l]: edges[l + 1]]
+        zl[l] = filter_z(stilde, Sn, hb, n, g["df"])
+    z = zl.sum(axis=0)
+    chi2 = p / sig2 * np.sum(np.abs(zl - z[None, :] / p) ** 2, axis=0)
+    return chi2, zl
+
+
+# ---------------------------------------------------------------------------
 # Gradient of rho^2 with respect to (M_c, eta, t_c)  (reading R13)
 # ---------------------------------------------------------------------------
 def _spa_phase_and_partials(f: np.ndarray, mc: float, eta: float, tc: float):
@@ -340,5 +385,5 @@ __all__ = [
     "total_mass_from_mc_eta", "f_isco", "band_lo", "band", "spa_phase",
     "spa_amplitude", "spa_template", "quadrature_partner", "sigma_sq",
     "inverse_dft", "filter_z", "filter_z_literal", "snr", "peak", "filter_unit",
-    "snr_sq", "snr_sq_fd_grad", "template_metric", "naive_dft",
+    "snr_sq", "snr_sq_fd_grad", "template_metric", "naive_dft", "chisq_band_edges", "chisq_series",
 ]

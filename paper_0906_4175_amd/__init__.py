@@ -25,7 +25,7 @@ from . import _lib as L
 
 __all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_plan", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
            "PRECISIONS", "version",
-           "template_metric"]
+           "template_metric", "chisq", "filter_chisq", "filter_chisq_workspace_bytes"]
 
 PRECISIONS = {"fp64": L.MF_FP64, "fp32_ph64": L.MF_FP32_PH64, "fp32": L.MF_FP32}
 SIGMA_MODES = {"fp64": L.MF_SIGMA_FP64, "comp32": L.MF_SIGMA_COMP32}
@@ -202,7 +202,61 @@ def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, preci
     L.check(st)
     pk = peaks.view(bank.n_tmpl, n_seg, 2)
     ints = pk[..., 1].contiguous().view(torch.int32).view(bank.n_tmpl, n_seg, 2)
-    return {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "series": series}
+    return {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "series": series, "raw": peaks}
+
+
+def filter_chisq_workspace_bytes(grid: Grid, precision, n_tmpl: int, n_seg: int, p_bands: int = 16) -> int:
+    g = grid.c()
+    nb = int(_clib.mf_filter_chisq_workspace_bytes(C.byref(g), _prec(precision), int(n_tmpl), int(n_seg),
+                                                    int(p_bands)))
+    if nb == 0:
+        raise L.MfError(-1, "no band-mode workspace for these arguments (N, precision, p_bands in [2, 64])")
+    return nb
+
+
+def filter_chisq(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, prefix: torch.Tensor,
+                 precision="fp32_ph64", p_bands: int = 16, threshold: float = math.inf, window=None,
+                 series_units=None, workspace: torch.Tensor | None = None):
+    """:func:`filter` plus the chi^2 of Eq. (5) at every sample (p_bands equal-sigma^2 bands).
+
+    prefix: the prefix array of :func:`psd` (prefix=True).  Returns the dict of
+    :func:`filter` plus "chisq" [n_tmpl, n_seg] float64 (chi^2 at each peak) and
+    "chisq_series" ([n_series, N], or None).
+    """
+    prec = _prec(precision)
+    _require_cuda(stilde, Sn, prefix)
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous() or stilde.shape[-1] != grid.n // 2 + 1:
+        raise ValueError(f"stilde must be contiguous {_cdtype(prec)} of shape [n_seg, {grid.n // 2 + 1}]")
+    n_seg = int(stilde.shape[0])
+    dev = stilde.device
+    n_units = bank.n_tmpl * n_seg
+    need = filter_chisq_workspace_bytes(grid, prec, bank.n_tmpl, n_seg, p_bands)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    peaks = torch.empty(2 * n_units, dtype=torch.float64, device=dev)
+    chisq = torch.empty((bank.n_tmpl, n_seg), dtype=torch.float64, device=dev)
+    opts = L.MfFilterOpts(float(threshold), 0, 0, None, 0)
+    if window is not None:
+        opts.j_begin, opts.j_end = int(window[0]), int(window[1])
+    series = chi_series = su = None
+    if series_units is not None:
+        su = torch.as_tensor(np.asarray(series_units, dtype=np.int32), device=dev)
+        sdt = torch.float64 if prec == L.MF_FP64 else torch.float32
+        series = torch.empty((su.numel(), grid.n), dtype=sdt, device=dev)
+        chi_series = torch.empty_like(series)
+        opts.series_units_dev = su.data_ptr()
+        opts.n_series = su.numel()
+    g = grid.c()
+    L.check(_clib.mf_filter_chisq(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn),
+                                  _ptr(prefix), prec, int(p_bands), C.byref(opts), _ptr(workspace),
+                                  workspace.numel(), _ptr(peaks), _ptr(chisq), _ptr(series), _ptr(chi_series),
+                                  _stream(dev)))
+    pk = peaks.view(bank.n_tmpl, n_seg, 2)
+    ints = pk[..., 1].contiguous().view(torch.int32).view(bank.n_tmpl, n_seg, 2)
+    return {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "series": series, "raw": peaks,
+            "chisq": chisq, "chisq_series": chi_series}
 
 
 def ifft(q: torch.Tensor, precision="fp32_ph64", workspace: torch.Tensor | None = None) -> torch.Tensor:
@@ -249,6 +303,29 @@ def snr_sq(grid: Grid, theta: torch.Tensor, seg: torch.Tensor, stilde: torch.Ten
                           _ptr(Sn), prec, _ptr(Z), _ptr(F), _ptr(gbar), _ptr(grad), _stream(dev))
     L.check(st)
     return F, Z, grad
+
+
+def chisq(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, prefix: torch.Tensor, peaks,
+          precision="fp32_ph64", p_bands: int = 16):
+    """chi^2 of Eq. (5) at each unit's peak sample; returns (chi2, rho) [n_tmpl, n_seg] float64.
+
+    peaks: the dict returned by :func:`filter` (its raw peak records are reused).
+    prefix: the prefix array of :func:`psd` (prefix=True).
+    """
+    prec = _prec(precision)
+    _require_cuda(stilde, Sn, prefix)
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous():
+        raise ValueError(f"stilde must be contiguous {_cdtype(prec)}")
+    n_seg = int(stilde.shape[0])
+    raw = peaks["raw"]
+    out = torch.empty((bank.n_tmpl, n_seg), dtype=torch.float64, device=stilde.device)
+    rho = torch.empty_like(out)
+    g = grid.c()
+    L.check(_clib.mf_chisq(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn), _ptr(prefix),
+                           prec, int(p_bands), _ptr(raw), _ptr(out), _ptr(rho), _stream(stilde.device)))
+    return out, rho
 
 
 def template_metric(grid: Grid, theta: torch.Tensor, Sn: torch.Tensor, khi: torch.Tensor) -> torch.Tensor:

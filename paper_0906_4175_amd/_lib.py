@@ -43,7 +43,7 @@ EXPORTS = [
     "mf_last_error", "mf_version", "mf_bank_bytes", "mf_filter_workspace_bytes", "mf_psd",
     "mf_spa_bank", "mf_filter", "mf_ifft_workspace_bytes", "mf_ifft", "mf_snr_grad",
     "mf_timing_enable", "mf_timing_read", "mf_probe_copy", "mf_filter_plan", "mf_plan_candidates", "mf_set_plan",
-    "mf_template_metric",
+    "mf_template_metric", "mf_chisq", "mf_filter_chisq", "mf_filter_chisq_workspace_bytes",
 ]
 
 _lib = None
@@ -90,6 +90,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_plan_candidates.argtypes = [P(MfGrid), C.c_int, P(i32), i32]
     lib.mf_set_plan.restype = C.c_int
     lib.mf_set_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
+    lib.mf_chisq.restype = C.c_int
+    lib.mf_chisq.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, vp, C.c_int, i32, vp, vp, vp, vp]
+    lib.mf_filter_chisq_workspace_bytes.restype = sz
+    lib.mf_filter_chisq_workspace_bytes.argtypes = [P(MfGrid), C.c_int, i64, i64, i32]
+    lib.mf_filter_chisq.restype = C.c_int
+    lib.mf_filter_chisq.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, vp, C.c_int, i32, P(MfFilterOpts), vp, sz, vp,
+                                    vp, vp, vp, vp]
     lib.mf_template_metric.restype = C.c_int
     lib.mf_template_metric.argtypes = [P(MfGrid), vp, vp, i64, vp, vp, vp]
     lib.mf_probe_copy.restype = C.c_int

@@ -1,0 +1,129 @@
+// chi^2 time-frequency veto of arXiv:0906.4175, Eq. (5) (Sec. 1.2), evaluated
+// at each (template, segment) unit's peak sample j:
+//   z_l(j) = 4 df sum_{k in band l} conj(h_k) s_k / S_k e^{2 pi i j k / N}
+//   chi^2  = p / sigma^2 sum_l |z_l - z / p|^2 = p / sigma^2 (sum_l |z_l|^2 - |z|^2 / p),
+// using sum_l z_l = z.  The p bands split the template's band into equal
+// shares of sigma^2 (Eq. (4)); a bin belongs to the band in which the sum of
+// f^{-7/3}/S over the bins before it falls.  Band edges come from binary
+// searches in the FP64 prefix sums of mf_psd.  One work-group per unit; FP64
+// phase (the time shift j k / N is reduced exactly in integers), FP64 sums.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "mf_device.hpp"
+#include "mf_internal.hpp"
+
+namespace mf {
+
+constexpr int kMaxBands = 64;
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) tot += scratch[w];
+    return tot;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_chisq(int64_t n, double df, const mf_bank_entry* bank, int64_t n_tmpl,
+                                              int64_t n_seg, const cx<T>* stilde, const double* Sn, const double* P,
+                                              int p, const mf_peak* peaks, double* chisq, double* rho_out) {
+    __shared__ int64_t edge[kMaxBands + 1];
+    __shared__ double zr[kMaxBands], zi[kMaxBands];
+    __shared__ double scratch[NT / 64];
+    const int tid = threadIdx.x;
+    const int64_t u = blockIdx.x;  // public unit id t * n_seg + s
+    const int64_t t = u / n_seg, s = u % n_seg;
+    const mf_bank_entry e = bank[t];
+    const int64_t klo = e.k_lo, khi = e.k_hi;
+    const int64_t j = peaks[u].j;
+    if (j < 0 || j >= n || khi > n / 2 - 1 || klo < 1 || khi < klo) {
+        if (tid == 0) {
+            chisq[u] = NAN;
+            if (rho_out) rho_out[u] = NAN;
+        }
+        return;
+    }
+    // equal-share band edges: e_l = min{k : P[k-1] - P[klo-1] >= l/p * (P[khi] - P[klo-1])}
+    if (tid == 0) {
+        edge[0] = klo;
+        edge[p] = khi + 1;
+    }
+    if (tid >= 1 && tid < p) {
+        const double base = P[klo - 1];
+        const double target = (double)tid / (double)p * (P[khi] - base);
+        int64_t lo = klo + 1, hi = khi + 1;  // answer in [klo+1, khi+1]
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (P[mid - 1] - base >= target) hi = mid; else lo = mid + 1;
+        }
+        edge[tid] = lo;
+    }
+    __syncthreads();
+    const PhaseCoef pc = load_coef(e);
+    const double amp0 = pow(df, -7.0 / 6.0);
+    const cx<T>* sp = stilde + s * (n / 2 + 1);
+    for (int l = 0; l < p; ++l) {
+        double ar = 0.0, ai = 0.0;
+        for (int64_t k = edge[l] + tid; k < edge[l + 1]; k += NT) {
+            const double kd = (double)k;
+            const double u3 = inv_cbrt_f64_full(kd);
+            double ph = spa_cycles_f64(pc, kd);
+            ph -= rint(ph);
+            double sh = (double)((j * k) % n) / (double)n;  // exact fraction of a cycle
+            ph += sh;
+            ph -= rint(ph);
+            double sn, cs;
+            sincospi(2.0 * ph, &sn, &cs);
+            const double a = amp0 * u3 * u3 * u3 * sqrt(u3);
+            const double g = 4.0 * df * a / Sn[k];
+            const cx<T> sv = sp[k];
+            const double wr = (double)sv.x * g, wi = (double)sv.y * g;
+            ar += wr * cs - wi * sn;
+            ai += wr * sn + wi * cs;
+        }
+        ar = block_sum<NT>(ar, scratch);
+        ai = block_sum<NT>(ai, scratch);
+        if (tid == 0) {
+            zr[l] = ar;
+            zi[l] = ai;
+        }
+    }
+    if (tid == 0) {
+        double sr = 0.0, si = 0.0, sq = 0.0;
+        for (int l = 0; l < p; ++l) {
+            sr += zr[l];
+            si += zi[l];
+            sq += zr[l] * zr[l] + zi[l] * zi[l];
+        }
+        const double s2 = e.sigma * e.sigma;
+        const double zz = sr * sr + si * si;
+        chisq[u] = (double)p / s2 * (sq - zz / (double)p);
+        if (rho_out) rho_out[u] = sqrt(zz) / e.sigma;
+    }
+}
+
+hipError_t launch_chisq(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
+                        const void* stilde, int64_t n_seg, const double* Sn, const double* prefix, int p,
+                        const mf_peak* peaks, double* chisq, double* rho, hipStream_t s) {
+    const double df = fs / (double)n;
+    constexpr int NT = 256;
+    const unsigned blocks = (unsigned)(n_tmpl * n_seg);
+    if (prec == MF_FP64)
+        hipLaunchKernelGGL((k_chisq<double, NT>), dim3(blocks), dim3(NT), 0, s, n, df, bank, n_tmpl, n_seg,
+                           (const cx<double>*)stilde, Sn, prefix, p, peaks, chisq, rho);
+    else
+        hipLaunchKernelGGL((k_chisq<float, NT>), dim3(blocks), dim3(NT), 0, s, n, df, bank, n_tmpl, n_seg,
+                           (const cx<float>*)stilde, Sn, prefix, p, peaks, chisq, rho);
+    return hipGetLastError();
+}
+
+}  // namespace mf

@@ -18,466 +18,18 @@
 // last) whose butterflies live in registers, with LDS between stages.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-#include <utility>
-
-#include "mf_device.hpp"
-#include "mf_internal.hpp"
+#include "filter_tiles.hpp"
 
 namespace mf {
-
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
-struct Partial64 {
-    double zz;
-    int32_t j;
-    int32_t cnt;
-};
-
-// Weight of the input-index digit that stage s of an L-point Stockham
-// transform consumes: L / (span * radix).
-__host__ __device__ constexpr int digit_weight(int L, int s) { return L / (span_before(L, s) * radix_at(L, s)); }
-
-// Stage twiddle tables, one contiguous table per stage s >= 1:
-// e^{+2 pi i k / (span_s R_s)} for k < span_s, so that the lanes of a
-// butterfly row read consecutive entries.
-__host__ __device__ constexpr int tw_offset(int L, int s) {
-    int off = 0;
-    for (int i = 1; i < s; ++i) off += span_before(L, i);
-    return off;
-}
-__host__ __device__ constexpr int tw_total(int L) { return tw_offset(L, num_stages(L)) + 1; }
-
-template <typename T, int L>
-__device__ __forceinline__ void fill_stage_twiddles(cx<T>* tw, int tid, int nt) {
-    constexpr int NS = num_stages(L);
-    for (int m = tid; m < tw_total(L); m += nt) {
-        int s = 1;
-#pragma unroll
-        for (int i = 2; i < NS; ++i) s = m >= tw_offset(L, i) ? i : s;
-        const int k = m - tw_offset(L, s);
-        const int M = span_before(L, s) * radix_at(L, s);
-        tw[m] = root_of_unity((T)k / (T)M);
-    }
-}
-
-// p[r] = w^r for r = 0..R-1 by a binary tree of products (depth log2 r).
-template <int R, typename T>
-__device__ __forceinline__ void powers(cx<T> w, cx<T>* p) {
-    p[0] = cx<T>{T(1), T(0)};
-    if constexpr (R > 1) p[1] = w;
-#pragma unroll
-    for (int r = 2; r < R; ++r) p[r] = cmul(p[r / 2], p[r - r / 2]);
-}
-
-__host__ __device__ constexpr int pad16(int k) { return k + (k >> 4); }
-
-__device__ __forceinline__ bool better64(double zz, int j, double bzz, int bj) {
-    const bool an = zz != zz, bn = bzz != bzz;
-    if (an != bn) return an;
-    if (an) return j < bj;
-    return zz > bzz || (zz == bzz && j < bj);
-}
-
-// ---------------------------------------------------------------------------
-// Pass 1 tile: C adjacent columns k2 of one unit.
-// PH: 0 = FP64 phase, 1 = FP32 phase.  RAW: input is a full N-point spectrum
-// (diagnostic inverse DFT) instead of the template x weight product.
-// Output: Y[j1][k2] = sum_k1 q[N2 k1 + k2] e^{2 pi i j1 k1 / N1}.
-// ---------------------------------------------------------------------------
-template <typename T, int PH, bool RAW, int N1, int N2, int C, int NT>
-struct Pass1 {
-    static constexpr int64_t N = (int64_t)N1 * N2;
-    static constexpr int NS = num_stages(N1);
-    static constexpr int TW = tw_total(N1);
-    static constexpr size_t SMEM = (size_t)(N1 * C + TW) * sizeof(cx<T>);
-
-    __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
-        cx<T>* buf = (cx<T>*)smem;
-        cx<T>* tw = buf + N1 * C;
-        const int tid = threadIdx.x;
-        const int k2_0 = tile * C;
-        const int64_t u = a.unit0 + ul;
-
-        PhaseCoef coef{};
-        int64_t klo = 0, khi = -1;
-        const cx<T>* w = nullptr;
-        const cx<T>* qin = nullptr;
-        if constexpr (RAW) {
-            qin = (const cx<T>*)a.raw_in + u * N;
-        } else {
-            const int64_t t = u % a.n_tmpl;
-            const int64_t s = u / a.n_tmpl;
-            const mf_bank_entry e = a.bank[t];
-            coef = load_coef(e);
-            klo = e.k_lo;
-            khi = e.k_hi;
-            w = (const cx<T>*)a.wgt + s * (N / 2 + 1);
-            if (tile == 0 && tid == 0 && a.keys != nullptr) {
-                a.keys[u] = 0ull;
-                a.counts[u] = 0u;
-            }
-        }
-        cx<T>* inter = (cx<T>*)a.inter + ul * N;
-
-        static_for<0, NS>([&](auto S_) {
-            constexpr int s = decltype(S_)::value;
-            constexpr int R = radix_at(N1, s);
-            constexpr int NSPAN = span_before(N1, s);
-            constexpr int NBF = C * N1 / R;
-            constexpr int BPT = (NBF + NT - 1) / NT;
-            cx<T> v[BPT][R];
-#pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                const int bf = tid + i * NT;
-                if (NBF % NT == 0 || bf < NBF) {
-                    const int c = bf % C;
-                    const int j = bf / C;
-                    if constexpr (s == 0) {
-                        const int64_t k2 = k2_0 + c;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const int64_t k1 = j + r * (N1 / R);
-                            if constexpr (RAW) {
-                                v[i][r] = qin[k1 * N2 + k2];
-                            } else {
-                                v[i][r] = cx<T>{T(0), T(0)};
-                                if (r < R / 2) {  // k1 < N1/2: non-negative frequencies only
-                                    const int64_t k = k1 * N2 + k2;
-                                    if (k >= klo && k <= khi) {
-                                        cx<T> rotor;
-                                        if constexpr (PH == 0) {
-                                            rotor = spa_rotor_ph64<T>(coef, (double)k);
-                                        } else {
-                                            rotor = spa_rotor_ph32(coef, (float)k);
-                                        }
-                                        v[i][r] = cmul(rotor, w[k]);
-                                    }
-                                }
-                            }
-                        }
-                    } else {
-                        const int k = j % NSPAN;
-                        const cx<T>* src = buf + j * C + c;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) v[i][r] = src[r * (N1 / R) * C];
-                        cx<T> p[R];
-                        powers<R>(tw[tw_offset(N1, s) + k], p);
-#pragma unroll
-                        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
-                    }
-                    IDft<R, T>::run(v[i]);
-                }
-            }
-            if constexpr (s == 0) fill_stage_twiddles<T, N1>(tw, tid, NT);
-            if constexpr (s == NS - 1) {
-#pragma unroll
-                for (int i = 0; i < BPT; ++i) {
-                    const int bf = tid + i * NT;
-                    if (NBF % NT == 0 || bf < NBF) {
-                        const int c = bf % C;
-                        const int j = bf / C;
-                        cx<T>* dst = inter + (int64_t)j * N2 + k2_0 + c;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) dst[(int64_t)r * NSPAN * N2] = v[i][r];
-                    }
-                }
-            } else {
-                __syncthreads();
-#pragma unroll
-                for (int i = 0; i < BPT; ++i) {
-                    const int bf = tid + i * NT;
-                    if (NBF % NT == 0 || bf < NBF) {
-                        const int c = bf % C;
-                        const int j = bf / C;
-                        const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
-                        cx<T>* dst = buf + idxD * C + c;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) dst[r * NSPAN * C] = v[i][r];
-                    }
-                }
-                __syncthreads();
-            }
-        });
-    }
-};
-
-// ---------------------------------------------------------------------------
-// Pass 2 tile: B rows j1 of one unit.
-// Row j1: z[j1 + N1 j2] = sum_k2 (Y[j1][k2] t^k2) e^{2 pi i j2 k2 / N2}, t = e^{2 pi i j1 / N}.
-// The four-step factor t^k2 is folded into the stage twiddles: writing k2 in
-// the mixed radix of the stages, stage s multiplies its input r by
-// (w_s t^{weight_s})^r with weight_s = N2 / (span_s R_s), so no separate
-// twiddle pass is needed and the result is exact (not only up to a phase).
-// The last stage squares |z| and reduces (max |z|^2, lowest index, count).
-// ---------------------------------------------------------------------------
-template <typename T, bool RAW, int N1, int N2, int B, int NT>
-struct Pass2 {
-    static constexpr int64_t N = (int64_t)N1 * N2;
-    static constexpr int NS = num_stages(N2);
-    static constexpr int PN2 = pad16(N2);
-    static constexpr int NWAVE = NT / 64;
-    static constexpr int TW = tw_total(N2);
-    static constexpr bool F64 = std::is_same<T, double>::value;
-    static constexpr size_t SMEM =
-        (size_t)(B * PN2 + TW + B * NS) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
-    static_assert(B * NS <= NT, "one thread per (row, stage) factor");
-
-    // LDS element offset of padded index x + r * step when x's padding is known
-    template <int STEP>
-    __device__ static __forceinline__ int off(int x, int r) {
-        if constexpr (STEP % 16 == 0) {
-            return pad16(x) + r * pad16(STEP);
-        } else {
-            return pad16(x + r * STEP);
-        }
-    }
-
-    __device__ static void run(const FilterArgs& a, char* smem, int rb, int64_t ul) {
-        cx<T>* buf = (cx<T>*)smem;
-        cx<T>* tw = buf + B * PN2;
-        cx<T>* trow = tw + TW;  // [B][NS]: t^{weight_s} per row
-        unsigned long long* red_key = (unsigned long long*)(trow + B * NS);
-        double* red_zz = (double*)(red_key + NWAVE);
-        int* red_j = (int*)(red_zz + NWAVE);
-        unsigned int* red_cnt = (unsigned int*)(red_j + NWAVE);
-
-        const int tid = threadIdx.x;
-        const int64_t u = a.unit0 + ul;
-        const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
-
-        if (tid < B * NS) {
-            const int b = tid / NS, st = tid % NS;
-            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st);  // < N
-            trow[b * NS + st] = root_of_unity((T)m / (T)N);
-        }
-
-        T thr2 = T(0);
-        bool count_on = false;
-        const bool full_window = a.j_begin == 0 && a.j_end == N;
-        double sigma = 1.0;
-        float inv_sigma_f = 1.0f;
-        int slot = -1;
-        if constexpr (!RAW) {
-            const int64_t t = u % a.n_tmpl;
-            const mf_bank_entry e = a.bank[t];
-            sigma = e.sigma;
-            inv_sigma_f = e.inv_sigma;
-            const double th = a.rho_threshold * sigma;
-            thr2 = (T)(th * th);
-            count_on = a.rho_threshold < INFINITY;
-            const int64_t pub = t * a.n_seg + u / a.n_tmpl;  // public unit id t * n_seg + s
-            for (int i = 0; i < a.n_series; ++i)
-                if (a.series_units[i] == pub) slot = i;
-        }
-        unsigned long long best_key = 0ull;
-        double best_zz = -1.0;
-        int best_j = 0x7fffffff;
-        unsigned int cnt = 0u;
-        __syncthreads();
-
-        static_for<0, NS>([&](auto S_) {
-            constexpr int s = decltype(S_)::value;
-            constexpr int R = radix_at(N2, s);
-            constexpr int NSPAN = span_before(N2, s);
-            constexpr int NBF = B * N2 / R;
-            constexpr int BPT = (NBF + NT - 1) / NT;
-            constexpr int PER_ROW = N2 / R;
-            cx<T> v[BPT][R];
-#pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                const int bf = tid + i * NT;
-                if (NBF % NT == 0 || bf < NBF) {
-                    const int j = bf % PER_ROW;
-                    const int b = bf / PER_ROW;
-                    cx<T> base = trow[b * NS + s];
-                    if constexpr (s == 0) {
-                        const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
-                    } else {
-                        const int k = j % NSPAN;
-                        const cx<T>* src = buf + b * PN2;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
-                        base = cmul(tw[tw_offset(N2, s) + k], base);
-                    }
-                    cx<T> p[R];
-                    powers<R>(base, p);
-#pragma unroll
-                    for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
-                    IDft<R, T>::run(v[i]);
-                }
-            }
-            if constexpr (s == 0) fill_stage_twiddles<T, N2>(tw, tid, NT);
-            if constexpr (s == NS - 1) {
-#pragma unroll
-                for (int i = 0; i < BPT; ++i) {
-                    const int bf = tid + i * NT;
-                    if (NBF % NT == 0 || bf < NBF) {
-                        const int j = bf % PER_ROW;
-                        const int b = bf / PER_ROW;
-                        const int j1 = rb * B + b;
-                        // output r of this butterfly is time sample j1 + N1 (j + r NSPAN): increasing in r
-                        if constexpr (RAW) {
-#pragma unroll
-                            for (int r = 0; r < R; ++r)
-                                ((cx<T>*)a.raw_out)[u * N + j1 + (int64_t)N1 * (j + r * NSPAN)] = v[i][r];
-                        } else {
-                            T zz[R];
-#pragma unroll
-                            for (int r = 0; r < R; ++r) zz[r] = norm2(v[i][r]);
-                            if (slot >= 0) {
-#pragma unroll
-                                for (int r = 0; r < R; ++r) {
-                                    const int64_t jg = j1 + (int64_t)N1 * (j + r * NSPAN);
-                                    if constexpr (F64) {
-                                        ((double*)a.rho)[(int64_t)slot * N + jg] = sqrt(zz[r]) / sigma;
-                                    } else {
-                                        ((float*)a.rho)[(int64_t)slot * N + jg] = sqrtf(zz[r]) * inv_sigma_f;
-                                    }
-                                }
-                            }
-                            if (full_window) {
-                                if (count_on) {
-#pragma unroll
-                                    for (int r = 0; r < R; ++r) cnt += (zz[r] >= thr2) ? 1u : 0u;
-                                }
-                                if constexpr (F64) {
-#pragma unroll
-                                    for (int r = 0; r < R; ++r) {
-                                        const int jg = j1 + N1 * (j + r * NSPAN);
-                                        if (better64(zz[r], jg, best_zz, best_j)) {
-                                            best_zz = zz[r];
-                                            best_j = jg;
-                                        }
-                                    }
-                                } else {
-                                    // integer max of the non-negative float bits (NaN bits exceed +inf,
-                                    // so a NaN propagates), then the lowest r that attains it
-                                    unsigned int mb = __float_as_uint(zz[0]);
-#pragma unroll
-                                    for (int r = 1; r < R; ++r) mb = max(mb, __float_as_uint(zz[r]));
-                                    int rmin = R - 1;
-#pragma unroll
-                                    for (int r = R - 2; r >= 0; --r) rmin = __float_as_uint(zz[r]) == mb ? r : rmin;
-                                    const unsigned int jg = (unsigned int)(j1 + N1 * (j + rmin * NSPAN));
-                                    const unsigned long long key =
-                                        ((unsigned long long)mb << 32) | (unsigned long long)(0xffffffffu - jg);
-                                    best_key = key > best_key ? key : best_key;
-                                }
-                            } else {
-#pragma unroll
-                                for (int r = 0; r < R; ++r) {
-                                    const int jg = j1 + N1 * (j + r * NSPAN);
-                                    if (jg >= a.j_begin && jg < a.j_end) {
-                                        if (count_on) cnt += (zz[r] >= thr2) ? 1u : 0u;
-                                        if constexpr (F64) {
-                                            if (better64(zz[r], jg, best_zz, best_j)) {
-                                                best_zz = zz[r];
-                                                best_j = jg;
-                                            }
-                                        } else {
-                                            const unsigned long long key =
-                                                ((unsigned long long)__float_as_uint(zz[r]) << 32) |
-                                                (unsigned long long)(0xffffffffu - (unsigned int)jg);
-                                            best_key = key > best_key ? key : best_key;
-                                        }
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-            } else {
-                __syncthreads();
-#pragma unroll
-                for (int i = 0; i < BPT; ++i) {
-                    const int bf = tid + i * NT;
-                    if (NBF % NT == 0 || bf < NBF) {
-                        const int j = bf % PER_ROW;
-                        const int b = bf / PER_ROW;
-                        const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
-                        cx<T>* dst = buf + b * PN2;
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            if constexpr (NSPAN == 1 && R == 16) {
-                                dst[pad16(idxD) + r] = v[i][r];  // idxD = 16 j: r stays inside the 16-block
-                            } else {
-                                dst[off<NSPAN>(idxD, r)] = v[i][r];
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        });
-
-        if constexpr (!RAW) {
-            // work-group reduction: wave shuffles, then one LDS slot per wave
-            const int lane = tid & 63;
-            const int wave = tid >> 6;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                cnt += __shfl_xor(cnt, o, 64);
-                if constexpr (F64) {
-                    const double ozz = __shfl_xor(best_zz, o, 64);
-                    const int oj = __shfl_xor(best_j, o, 64);
-                    if (better64(ozz, oj, best_zz, best_j)) {
-                        best_zz = ozz;
-                        best_j = oj;
-                    }
-                } else {
-                    const unsigned long long ov = __shfl_xor(best_key, o, 64);
-                    best_key = ov > best_key ? ov : best_key;
-                }
-            }
-            if (lane == 0) {
-                red_cnt[wave] = cnt;
-                red_key[wave] = best_key;
-                red_zz[wave] = best_zz;
-                red_j[wave] = best_j;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                for (int wv = 1; wv < NWAVE; ++wv) {
-                    cnt += red_cnt[wv];
-                    if constexpr (F64) {
-                        if (better64(red_zz[wv], red_j[wv], best_zz, best_j)) {
-                            best_zz = red_zz[wv];
-                            best_j = red_j[wv];
-                        }
-                    } else {
-                        best_key = red_key[wv] > best_key ? red_key[wv] : best_key;
-                    }
-                }
-                if constexpr (F64) {
-                    // partials of every unit of the call: [n_units][N1 / B]
-                    Partial64* part = (Partial64*)a.partials + u * (N1 / B) + rb;
-                    *part = Partial64{best_zz, best_j, (int32_t)cnt};
-                } else {
-                    atomicMax(a.keys + u, best_key);
-                    if (cnt) atomicAdd(a.counts + u, cnt);
-                }
-            }
-        }
-    }
-};
 
 template <size_t A, size_t B>
 struct MaxSz {
     static constexpr size_t value = A > B ? A : B;
 };
 
-template <typename T, int PH, bool RAW, int N1, int N2, int C, int NT>
+template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
 __global__ void __launch_bounds__(NT) k_pass1(FilterArgs a) {
-    using P = Pass1<T, PH, RAW, N1, N2, C, NT>;
+    using P = Pass1<T, PH, MODE, N1, N2, C, NT>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
@@ -495,7 +47,7 @@ __global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
 // pass 1 with the arithmetic-bound pass 2.
 template <typename T, int PH, int N1, int N2, int C, int B, int NT>
 __global__ void __launch_bounds__(NT) k_step(FilterArgs a1, FilterArgs a2) {
-    using P1 = Pass1<T, PH, false, N1, N2, C, NT>;
+    using P1 = Pass1<T, PH, P1_PRODUCT, N1, N2, C, NT>;
     using P2 = Pass2<T, false, N1, N2, B, NT>;
     __shared__ __align__(16) char smem[MaxSz<P1::SMEM, P2::SMEM>::value];
     constexpr int W1 = N2 / C;  // pass-1 tiles per unit
@@ -682,12 +234,12 @@ FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t 
     return L;
 }
 
-template <typename T, int PH, bool RAW, int N1, int N2, int C>
+template <typename T, int PH, int MODE, int N1, int N2, int C>
 static hipError_t run_pass1(const FilterArgs& a, hipStream_t s) {
     static_assert(N2 % C == 0 && C <= N2, "pass-1 columns per work-group must tile N2");
     constexpr int NT = clamp_threads(C * N1 / 16);
     dim3 grid(N2 / C, (unsigned)a.units);
-    hipLaunchKernelGGL((k_pass1<T, PH, RAW, N1, N2, C, NT>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_pass1<T, PH, MODE, N1, N2, C, NT>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -703,9 +255,10 @@ static hipError_t run_pass2(const FilterArgs& a, hipStream_t s) {
 hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s) {
 #define MF_P1(T, N1, N2, C, B)                                                                                  \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {    \
-        if (raw) return run_pass1<T, 0, true, N1, N2, C>(a, s);                                                \
-        if (std::is_same<T, float>::value && prec == MF_FP32) return run_pass1<float, 1, false, N1, N2, C>(a, s); \
-        return run_pass1<T, 0, false, N1, N2, C>(a, s);                                                        \
+        if (raw) return run_pass1<T, 0, P1_RAW, N1, N2, C>(a, s);                                              \
+        if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
+            return run_pass1<float, 1, P1_PRODUCT, N1, N2, C>(a, s);                                           \
+        return run_pass1<T, 0, P1_PRODUCT, N1, N2, C>(a, s);                                                   \
     }
     MF_SHAPES(MF_P1)
 #undef MF_P1

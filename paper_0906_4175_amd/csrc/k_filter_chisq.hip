@@ -1,0 +1,502 @@
+// chi^2 time-frequency veto of arXiv:0906.4175, Eq. (5) (Sec. 1.2), over the
+// whole series: for every time sample j of every (template, segment) unit,
+//   chi^2(j) = p / sigma^2 sum_l |z_l(j) - z(j)/p|^2
+//            = (p sum_l |z_l(j)|^2 - |z(j)|^2) / sigma^2 ,   z = sum_l z_l,
+// where z_l is Eq. (1) restricted to band l of p bands with equal shares of
+// sigma^2 (Eq. (4)).  The paper runs one inverse FFT per band and a separate
+// accumulation kernel; here the p band transforms share the two-pass inverse
+// DFT of the matched filter (bins k = N2 k1 + k2, times j = j1 + N1 j2):
+//
+//  * The bands are contiguous in k and, except the widest, span only a few
+//    rows k1.  Pass 1 writes the template x weight product q (rows k1 < N1/2,
+//    once) and transforms only the widest band; its column-transform output
+//    goes to the intermediate as in the plain filter.
+//  * Pass 2 rebuilds row j1 of every other band directly from the few q rows
+//    it touches, Y_l[j1][k2] = sum_{k1 in band l} q[k1][k2] e^{2 pi i j1 k1/N1},
+//    runs the p row transforms, accumulates z and sum_l |z_l|^2 in registers
+//    and reduces |z|^2 (peak, threshold count, series) together with chi^2.
+//
+// Per unit this moves the product (written once, re-read from cache), one
+// intermediate and the weights instead of p intermediates.
+#include "filter_tiles.hpp"
+
+namespace mf {
+
+// Peak record of one pass-2 work-group in band mode: max |z|^2 (lowest index
+// on ties), chi^2 at that sample, threshold count.
+struct PartialChi {
+    double zz;
+    double chi2;
+    int32_t j;
+    int32_t cnt;
+};
+
+// Band table of one template: e_0 = k_lo < e_1 <= ... <= e_p = k_hi + 1 with
+// e_l = min{k : P[k-1] - P[k_lo-1] >= l/p (P[k_hi] - P[k_lo-1])} (a bin
+// belongs to the band in which the sigma^2 sum before it falls), then the
+// index of the band spanning the most rows of N2 bins.
+__global__ void __launch_bounds__(64) k_band_table(int64_t n, int n2, const mf_bank_entry* bank, const double* P,
+                                                   int p, int32_t* tab) {
+    __shared__ int64_t edge[65];
+    const int tid = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const mf_bank_entry e = bank[t];
+    const int64_t klo = e.k_lo, khi = e.k_hi;
+    int32_t* row = tab + t * (p + 2);
+    const bool valid = klo >= 1 && khi >= klo && khi <= n / 2 - 1;
+    if (!valid) {
+        // empty bands: every bin stays untouched and the unit outputs zero
+        for (int l = tid; l <= p; l += 64) row[l] = 1;
+        if (tid == 0) row[p + 1] = 0;
+        return;
+    }
+    if (tid == 0) {
+        edge[0] = klo;
+        edge[p] = khi + 1;
+    }
+    if (tid >= 1 && tid < p) {
+        const double base = P[klo - 1];
+        const double target = (double)tid / (double)p * (P[khi] - base);
+        int64_t lo = klo + 1, hi = khi + 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (P[mid - 1] - base >= target) hi = mid; else lo = mid + 1;
+        }
+        edge[tid] = lo;
+    }
+    __syncthreads();
+    for (int l = tid; l <= p; l += 64) row[l] = (int32_t)edge[l];
+    if (tid == 0) {
+        int wide = 0;
+        int64_t best = -1;
+        for (int l = 0; l < p; ++l) {
+            const int64_t rows = edge[l + 1] > edge[l] ? (edge[l + 1] - 1) / n2 - edge[l] / n2 + 1 : 0;
+            if (rows > best) {
+                best = rows;
+                wide = l;
+            }
+        }
+        row[p + 1] = wide;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2 tile in band mode: B rows j1 of one unit, all p bands.
+// ---------------------------------------------------------------------------
+template <typename T, int N1, int N2, int B, int NT>
+struct Pass2Band {
+    static constexpr int64_t N = (int64_t)N1 * N2;
+    static constexpr int NS = num_stages(N2);
+    static constexpr int PN2 = pad16(N2);
+    static constexpr int NWAVE = NT / 64;
+    static constexpr int TW = tw_total(N2);
+    static constexpr int HALF = N1 / 2;
+    static constexpr int RL = radix_at(N2, NS - 1);
+    static constexpr int NSPANL = span_before(N2, NS - 1);
+    static constexpr int PER_ROWL = N2 / RL;
+    static constexpr int NBFL = B * N2 / RL;
+    static constexpr int BPTL = (NBFL + NT - 1) / NT;
+    static constexpr bool F64 = std::is_same<T, double>::value;
+    static constexpr size_t SMEM =
+        (size_t)(B * PN2 + TW + B * NS + B * HALF) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
+    static_assert(B * NS <= NT, "one thread per (row, stage) factor");
+
+    template <int STEP>
+    __device__ static __forceinline__ int off(int x, int r) {
+        if constexpr (STEP % 16 == 0) {
+            return pad16(x) + r * pad16(STEP);
+        } else {
+            return pad16(x + r * STEP);
+        }
+    }
+
+    __device__ static void run(const FilterArgs& a, char* smem, int rb, int64_t ul) {
+        cx<T>* buf = (cx<T>*)smem;
+        cx<T>* tw = buf + B * PN2;
+        cx<T>* trow = tw + TW;   // [B][NS]: t^{weight_s} per row
+        cx<T>* om = trow + B * NS;  // [B][N1/2]: e^{2 pi i j1 k1 / N1}
+        double* red_zz = (double*)(om + B * HALF);
+        double* red_chi = red_zz + NWAVE;
+        int* red_j = (int*)(red_chi + NWAVE);
+        unsigned int* red_cnt = (unsigned int*)(red_j + NWAVE);
+
+        const int tid = threadIdx.x;
+        const int64_t u = a.unit0 + ul;
+        const int64_t t = u % a.n_tmpl;
+        const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
+        const cx<T>* q = (const cx<T>*)a.qbuf + ul * (N / 2);
+        const int P = a.p_bands;
+        const int32_t* tab = a.band_tab + t * (P + 2);
+        const int wb = tab[P + 1];
+
+        if (tid < B * NS) {
+            const int b = tid / NS, st = tid % NS;
+            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st);  // < N
+            trow[b * NS + st] = root_of_unity((T)m / (T)N);
+        }
+        for (int m = tid; m < B * HALF; m += NT) {
+            const int b = m / HALF, k1 = m % HALF;
+            const int64_t jk = (int64_t)(rb * B + b) * k1 % N1;  // exact reduction
+            om[m] = root_of_unity((T)jk / (T)N1);
+        }
+        fill_stage_twiddles<T, N2>(tw, tid, NT);
+
+        const mf_bank_entry e = a.bank[t];
+        const double sigma = e.sigma;
+        const float inv_sigma_f = e.inv_sigma;
+        const double th = a.rho_threshold * sigma;
+        const T thr2 = (T)(th * th);
+        const bool count_on = a.rho_threshold < INFINITY;
+        const int64_t pub = t * a.n_seg + u / a.n_tmpl;
+        int slot = -1;
+        for (int i = 0; i < a.n_series; ++i)
+            if (a.series_units[i] == pub) slot = i;
+
+        cx<T> accz[BPTL][RL];
+        T accq[BPTL][RL];
+#pragma unroll
+        for (int i = 0; i < BPTL; ++i)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                accz[i][r] = cx<T>{T(0), T(0)};
+                accq[i][r] = T(0);
+            }
+        __syncthreads();
+
+        for (int l = 0; l < P; ++l) {
+            const int64_t e0 = tab[l], e1 = tab[l + 1];
+            if (e0 >= e1) continue;  // empty band (uniform over the work-group)
+            const bool from_inter = l == wb;
+            const int r0 = (int)(e0 / N2), r1 = (int)((e1 - 1) / N2);  // r1 < N1/2
+            static_for<0, NS>([&](auto S_) {
+                constexpr int s = decltype(S_)::value;
+                constexpr int R = radix_at(N2, s);
+                constexpr int NSPAN = span_before(N2, s);
+                constexpr int NBF = B * N2 / R;
+                constexpr int BPT = (NBF + NT - 1) / NT;
+                constexpr int PER_ROW = N2 / R;
+                cx<T> v[BPT][R];
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int bf = tid + i * NT;
+                    if (NBF % NT == 0 || bf < NBF) {
+                        const int j = bf % PER_ROW;
+                        const int b = bf / PER_ROW;
+                        cx<T> base = trow[b * NS + s];
+                        if constexpr (s == 0) {
+                            if (from_inter) {
+                                const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
+#pragma unroll
+                                for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < R; ++r) v[i][r] = cx<T>{T(0), T(0)};
+                                for (int k1 = r0; k1 <= r1; ++k1) {
+                                    const cx<T> w = om[b * HALF + k1];
+                                    const int64_t kb = (int64_t)k1 * N2 + j;
+#pragma unroll
+                                    for (int r = 0; r < R; ++r) {
+                                        const int64_t k = kb + r * PER_ROW;
+                                        if (k >= e0 && k < e1) v[i][r] = v[i][r] + cmul(q[k], w);
+                                    }
+                                }
+                            }
+                        } else {
+                            const int k = j % NSPAN;
+                            const cx<T>* src = buf + b * PN2;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
+                            base = cmul(tw[tw_offset(N2, s) + k], base);
+                        }
+                        cx<T> pw[R];
+                        powers<R>(base, pw);
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pw[r]);
+                        IDft<R, T>::run(v[i]);
+                    }
+                }
+                if constexpr (s == NS - 1) {
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            accz[i][r] = accz[i][r] + v[i][r];
+                            accq[i][r] += norm2(v[i][r]);
+                        }
+                    }
+                } else {
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i) {
+                        const int bf = tid + i * NT;
+                        if (NBF % NT == 0 || bf < NBF) {
+                            const int j = bf % PER_ROW;
+                            const int b = bf / PER_ROW;
+                            const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
+                            cx<T>* dst = buf + b * PN2;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                if constexpr (NSPAN == 1 && R == 16) {
+                                    dst[pad16(idxD) + r] = v[i][r];
+                                } else {
+                                    dst[off<NSPAN>(idxD, r)] = v[i][r];
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            });
+        }
+
+        // chi^2, rho, series, peak and threshold count of this tile
+        const double sig2 = sigma * sigma;
+        double best_zz = -1.0, best_chi = 0.0;
+        int best_j = 0x7fffffff;
+        unsigned int cnt = 0u;
+#pragma unroll
+        for (int i = 0; i < BPTL; ++i) {
+            const int bf = tid + i * NT;
+            if (NBFL % NT == 0 || bf < NBFL) {
+                const int j = bf % PER_ROWL;
+                const int b = bf / PER_ROWL;
+                const int j1 = rb * B + b;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int jg = j1 + N1 * (j + r * NSPANL);
+                    const T zz = norm2(accz[i][r]);
+                    const double chi = ((double)P * (double)accq[i][r] - (double)zz) / sig2;
+                    if (slot >= 0) {
+                        if constexpr (F64) {
+                            ((double*)a.rho)[(int64_t)slot * N + jg] = sqrt(zz) / sigma;
+                            ((double*)a.chi_series)[(int64_t)slot * N + jg] = chi;
+                        } else {
+                            ((float*)a.rho)[(int64_t)slot * N + jg] = sqrtf(zz) * inv_sigma_f;
+                            ((float*)a.chi_series)[(int64_t)slot * N + jg] = (float)chi;
+                        }
+                    }
+                    if (jg >= a.j_begin && jg < a.j_end) {
+                        if (count_on) cnt += (zz >= thr2) ? 1u : 0u;
+                        if (better64((double)zz, jg, best_zz, best_j)) {
+                            best_zz = (double)zz;
+                            best_j = jg;
+                            best_chi = chi;
+                        }
+                    }
+                }
+            }
+        }
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            cnt += __shfl_xor(cnt, o, 64);
+            const double ozz = __shfl_xor(best_zz, o, 64);
+            const double och = __shfl_xor(best_chi, o, 64);
+            const int oj = __shfl_xor(best_j, o, 64);
+            if (better64(ozz, oj, best_zz, best_j)) {
+                best_zz = ozz;
+                best_j = oj;
+                best_chi = och;
+            }
+        }
+        if (lane == 0) {
+            red_cnt[wave] = cnt;
+            red_zz[wave] = best_zz;
+            red_chi[wave] = best_chi;
+            red_j[wave] = best_j;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int wv = 1; wv < NWAVE; ++wv) {
+                cnt += red_cnt[wv];
+                if (better64(red_zz[wv], red_j[wv], best_zz, best_j)) {
+                    best_zz = red_zz[wv];
+                    best_j = red_j[wv];
+                    best_chi = red_chi[wv];
+                }
+            }
+            PartialChi* part = (PartialChi*)a.partials + u * (N1 / B) + rb;
+            *part = PartialChi{best_zz, best_chi, best_j, (int32_t)cnt};
+        }
+    }
+};
+
+template <typename T, int PH, int N1, int N2, int C, int NT>
+__global__ void __launch_bounds__(NT) k_pass1_band(FilterArgs a) {
+    using P = Pass1<T, PH, P1_BAND, N1, N2, C, NT>;
+    __shared__ __align__(16) char smem[P::SMEM];
+    P::run(a, smem, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int N1, int N2, int B, int NT>
+__global__ void __launch_bounds__(NT) k_pass2_band(FilterArgs a) {
+    using P = Pass2Band<T, N1, N2, B, NT>;
+    __shared__ __align__(16) char smem[P::SMEM];
+    P::run(a, smem, blockIdx.x, blockIdx.y);
+}
+
+// One 64-thread work-group per unit: peak over the partials (same comparison
+// as pass 2), chi^2 at the peak, threshold count.
+__global__ void __launch_bounds__(64) k_finalize_band(const PartialChi* part, int n_part, const mf_bank_entry* bank,
+                                                      int64_t n_tmpl, int64_t n_seg, mf_peak* peaks, double* chisq) {
+    const int64_t u = blockIdx.x;
+    const int64_t t = u % n_tmpl, s = u / n_tmpl;
+    double bzz = -1.0, bchi = 0.0;
+    int bj = 0x7fffffff;
+    long long cnt = 0;
+    for (int i = threadIdx.x; i < n_part; i += 64) {
+        const PartialChi p = part[u * n_part + i];
+        cnt += p.cnt;
+        if (better64(p.zz, p.j, bzz, bj)) {
+            bzz = p.zz;
+            bj = p.j;
+            bchi = p.chi2;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off, 64);
+        const double ozz = __shfl_xor(bzz, off, 64);
+        const double och = __shfl_xor(bchi, off, 64);
+        const int oj = __shfl_xor(bj, off, 64);
+        if (better64(ozz, oj, bzz, bj)) {
+            bzz = ozz;
+            bj = oj;
+            bchi = och;
+        }
+    }
+    if (threadIdx.x == 0) {
+        mf_peak o;
+        o.rho = sqrt(bzz) / bank[t].sigma;
+        o.j = bj;
+        o.n_above = (int32_t)cnt;
+        peaks[t * n_seg + s] = o;
+        chisq[t * n_seg + s] = bchi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+// One shape per N and precision (the default shape of the plain filter).
+#define MF_BAND_SHAPES(X)                                                                                   \
+    X(float, 32, 32, 16, 32) X(float, 32, 64, 16, 32) X(float, 64, 64, 16, 64) X(float, 64, 128, 16, 32)    \
+    X(float, 128, 128, 16, 32) X(float, 128, 256, 16, 16) X(float, 256, 256, 16, 16)                         \
+    X(float, 256, 512, 16, 8) X(float, 512, 512, 16, 8) X(float, 512, 1024, 16, 4)                            \
+    X(float, 256, 4096, 16, 1) X(float, 1024, 2048, 16, 2) X(float, 2048, 2048, 8, 2)                         \
+    X(double, 32, 32, 8, 32) X(double, 32, 64, 8, 32) X(double, 64, 64, 8, 64) X(double, 64, 128, 8, 32)     \
+    X(double, 128, 128, 8, 32) X(double, 128, 256, 8, 16) X(double, 256, 256, 8, 16)                          \
+    X(double, 256, 512, 8, 8) X(double, 512, 512, 8, 8) X(double, 512, 1024, 8, 4)                            \
+    X(double, 512, 2048, 8, 2) X(double, 1024, 2048, 4, 2) X(double, 2048, 2048, 2, 2)
+
+static constexpr int band_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024 : x); }
+
+static bool band_want(mf_precision prec, bool f64) { return (prec == MF_FP64) == f64; }
+
+Plan band_plan(int log2n, mf_precision prec) {
+    Plan p{};
+    p.log2n = -1;
+    bool found = false;
+#define MF_BFIRST(T, N1, N2, C, B)                                                                          \
+    if (!found && band_want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n) { \
+        p.n1 = N1;                                                                                          \
+        p.n2 = N2;                                                                                          \
+        p.c1 = C;                                                                                           \
+        p.b2 = B;                                                                                           \
+        p.nt1 = band_threads(C * N1 / 16);                                                                  \
+        p.nt2 = band_threads(B * N2 / 16);                                                                  \
+        p.log2n = log2n;                                                                                    \
+        found = true;                                                                                       \
+    }
+    MF_BAND_SHAPES(MF_BFIRST)
+#undef MF_BFIRST
+    if (!found) return p;
+    // About 256 MiB of product and intermediate per batch, so that pass 2
+    // finds most of what pass 1 wrote still in the last-level cache.
+    const size_t bytes_per_unit = ((size_t)3 << log2n) / 2 * cx_bytes(prec);
+    size_t u = ((size_t)256 << 20) / bytes_per_unit;
+    if (const char* e = getenv("MF_BAND_UNITS")) {
+        const long v = strtol(e, nullptr, 10);
+        if (v >= 1 && v <= 4096) u = (size_t)v;
+    }
+    p.units = (int)(u < 1 ? 1 : (u > 4096 ? 4096 : u));
+    p.fused = false;
+    return p;
+}
+
+static size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
+
+BandLayout band_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg, int p_bands) {
+    BandLayout L{};
+    const int64_t n_units = n_tmpl * n_seg;
+    const int64_t upb = n_units < p.units ? n_units : p.units;
+    L.units_per_batch = upb < 1 ? 1 : upb;
+    size_t off = 0;
+    L.off_w = off;
+    off = align256b(off + (size_t)n_seg * (size_t)(n / 2 + 1) * cx_bytes(prec));
+    L.off_tab = off;
+    off = align256b(off + (size_t)n_tmpl * (size_t)(p_bands + 2) * sizeof(int32_t));
+    L.off_q = off;
+    off = align256b(off + (size_t)L.units_per_batch * (size_t)(n / 2) * cx_bytes(prec));
+    L.off_inter = off;
+    off = align256b(off + (size_t)L.units_per_batch * (size_t)n * cx_bytes(prec));
+    L.off_part = off;
+    off = align256b(off + (size_t)n_units * (size_t)(p.n1 / p.b2) * sizeof(PartialChi));
+    L.total = off;
+    return L;
+}
+
+hipError_t launch_band_table(int64_t n, int n2, const mf_bank_entry* bank, int64_t n_tmpl, const double* prefix,
+                             int p, int32_t* tab, hipStream_t s) {
+    hipLaunchKernelGGL(k_band_table, dim3((unsigned)n_tmpl), dim3(64), 0, s, n, n2, bank, prefix, p, tab);
+    return hipGetLastError();
+}
+
+template <typename T, int PH, int N1, int N2, int C>
+static hipError_t run_pass1_band(const FilterArgs& a, hipStream_t s) {
+    static_assert(N2 % C == 0 && C <= N2, "pass-1 columns per work-group must tile N2");
+    constexpr int NT = band_threads(C * N1 / 16);
+    dim3 grid(N2 / C, (unsigned)a.units);
+    hipLaunchKernelGGL((k_pass1_band<T, PH, N1, N2, C, NT>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int N1, int N2, int B>
+static hipError_t run_pass2_band(const FilterArgs& a, hipStream_t s) {
+    static_assert(N1 % B == 0 && B <= N1, "pass-2 rows per work-group must tile N1");
+    constexpr int NT = band_threads(B * N2 / 16);
+    dim3 grid(N1 / B, (unsigned)a.units);
+    hipLaunchKernelGGL((k_pass2_band<T, N1, N2, B, NT>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass1_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s) {
+#define MF_BP1(T, N1, N2, C, B)                                                                                 \
+    if (band_want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C &&          \
+        p.b2 == B) {                                                                                          \
+        if (std::is_same<T, float>::value && prec == MF_FP32) return run_pass1_band<float, 1, N1, N2, C>(a, s); \
+        return run_pass1_band<T, 0, N1, N2, C>(a, s);                                                         \
+    }
+    MF_BAND_SHAPES(MF_BP1)
+#undef MF_BP1
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass2_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s) {
+#define MF_BP2(T, N1, N2, C, B)                                                                        \
+    if (band_want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && \
+        p.b2 == B)                                                                                   \
+        return run_pass2_band<T, N1, N2, B>(a, s);
+    MF_BAND_SHAPES(MF_BP2)
+#undef MF_BP2
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_band(const Plan& p, const FilterArgs& a, mf_peak* peaks, double* chisq, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_band, dim3((unsigned)a.n_units), dim3(64), 0, s, (const PartialChi*)a.partials,
+                       p.n1 / p.b2, a.bank, a.n_tmpl, a.n_seg, peaks, chisq);
+    return hipGetLastError();
+}
+
+}  // namespace mf

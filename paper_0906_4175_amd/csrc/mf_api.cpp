@@ -45,6 +45,29 @@ hipEvent_t timing_event() {
     return e;
 }
 
+mf_status fail(mf_status st, const char* fmt, ...);
+mf_status hip_fail(hipError_t e, const char* where);
+
+// Runs launch(); every stride-th call gets an event pair on the stream
+// (measurement hook).  units1 / units2: units of the pass-1 / pass-2 roles.
+template <typename F>
+mf_status timed_launch(hipStream_t s, int64_t units1, int64_t units2, F&& launch) {
+    const bool timed = g_timing.stride > 0 && (g_timing.batch_counter++ % g_timing.stride) == 0;
+    TimedLaunch t{};
+    if (timed) {
+        t = TimedLaunch{timing_event(), timing_event(), units1, units2};
+        if (!t.start || !t.stop) return fail(MF_E_HIP, "timing event creation failed");
+        hipEventRecord(t.start, s);
+    }
+    hipError_t le = launch();
+    if (le != hipSuccess) return hip_fail(le, "pass launch");
+    if (timed) {
+        hipEventRecord(t.stop, s);
+        g_timing.pending.push_back(t);
+    }
+    return MF_OK;
+}
+
 mf_status fail(mf_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -465,6 +488,109 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
     hipError_t e = mf::launch_snr_grad(grid->n, grid->fs, klo, prec, theta_dev, khi_dev, seg_dev, n, stilde_dev, n_seg, Sn_dev,
                                        Z_dev, rho2_dev, gbar_dev, grad_dev, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "mf_snr_grad");
+    return ok();
+}
+
+size_t mf_filter_chisq_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl, int64_t n_seg,
+                                       int32_t p_bands) {
+    int l, klo;
+    if (check_grid(grid, &l, &klo) != MF_OK || !valid_prec(prec) || n_tmpl < 1 || n_seg < 1 || p_bands < 2 ||
+        p_bands > 64)
+        return 0;
+    const mf::Plan p = mf::band_plan(l, prec);
+    if (p.log2n != l) return 0;
+    return mf::band_layout(p, prec, grid->n, n_tmpl, n_seg, p_bands).total;
+}
+
+mf_status mf_filter_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
+                          int64_t n_seg, const double* Sn_dev, const double* prefix_dev, mf_precision prec,
+                          int32_t p_bands, const mf_filter_opts* opts, void* workspace_dev, size_t workspace_bytes,
+                          mf_peak* peaks_dev, double* chisq_dev, void* rho_dev, void* chisq_series_dev,
+                          mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!bank_dev || !stilde_dev || !Sn_dev || !prefix_dev || !peaks_dev || !chisq_dev || !workspace_dev)
+        return fail(MF_E_ARG, "null pointer argument");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (p_bands < 2 || p_bands > 64) return fail(MF_E_ARG, "p_bands=%d outside [2, 64]", (int)p_bands);
+    if (n_tmpl < 1 || n_seg < 1 || n_tmpl * n_seg > (int64_t(1) << 31) - 1)
+        return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld", (long long)n_tmpl, (long long)n_seg);
+    const int64_t n = grid->n;
+    mf_filter_opts o{INFINITY, 0, 0, nullptr, 0};
+    if (opts) o = *opts;
+    if (o.j_end == 0) o.j_end = n;
+    if (o.j_begin < 0 || o.j_end > n || o.j_begin >= o.j_end)
+        return fail(MF_E_SHAPE, "window [%lld, %lld) outside [0, %lld)", (long long)o.j_begin, (long long)o.j_end,
+                    (long long)n);
+    if (o.rho_threshold != o.rho_threshold) return fail(MF_E_ARG, "rho_threshold is NaN");
+    if (o.n_series < 0) return fail(MF_E_ARG, "n_series < 0");
+    if (o.n_series > 0 && (!o.series_units_dev || !rho_dev || !chisq_series_dev))
+        return fail(MF_E_ARG, "series requested without series_units_dev / rho_dev / chisq_series_dev");
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(MF_E_ARG, "workspace must be 256-byte aligned");
+    const mf::Plan p = mf::band_plan(l, prec);
+    if (p.log2n != l) return fail(MF_E_UNSUPPORTED, "no band-mode plan for n=%lld", (long long)n);
+    const mf::BandLayout L = mf::band_layout(p, prec, n, n_tmpl, n_seg, p_bands);
+    if (L.units_per_batch * (int64_t)(p.n2 / p.c1 + p.n1 / p.b2) > (int64_t)0x7fffffff)
+        return fail(MF_E_UNSUPPORTED, "batch too large for one launch");
+    if (workspace_bytes < L.total)
+        return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+
+    char* ws = (char*)workspace_dev;
+    mf::FilterArgs a{};
+    a.wgt = ws + L.off_w;
+    a.bank = (const mf_bank_entry*)bank_dev;
+    a.inter = ws + L.off_inter;
+    a.partials = ws + L.off_part;
+    a.n_tmpl = n_tmpl;
+    a.n_seg = n_seg;
+    a.n_units = n_tmpl * n_seg;
+    a.j_begin = o.j_begin;
+    a.j_end = o.j_end;
+    a.rho_threshold = o.rho_threshold;
+    a.series_units = o.series_units_dev;
+    a.n_series = o.n_series;
+    a.rho = rho_dev;
+    a.band_tab = (const int32_t*)(ws + L.off_tab);
+    a.p_bands = p_bands;
+    a.qbuf = ws + L.off_q;
+    a.chi_series = chisq_series_dev;
+
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter_chisq weights");
+    e = mf::launch_band_table(n, p.n2, a.bank, n_tmpl, prefix_dev, p_bands, (int32_t*)(ws + L.off_tab), s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter_chisq band table");
+    const int64_t upb = L.units_per_batch;
+    for (int64_t u0 = 0; u0 < a.n_units; u0 += upb) {
+        mf::FilterArgs x = a;
+        x.unit0 = u0;
+        x.units = (a.n_units - u0) < upb ? (a.n_units - u0) : upb;
+        st = timed_launch(s, x.units, 0, [&] { return mf::launch_pass1_band(p, prec, x, s); });
+        if (st != MF_OK) return st;
+        st = timed_launch(s, 0, x.units, [&] { return mf::launch_pass2_band(p, prec, x, s); });
+        if (st != MF_OK) return st;
+    }
+    e = mf::launch_finalize_band(p, a, peaks_dev, chisq_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter_chisq finalize");
+    return ok();
+}
+
+mf_status mf_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev, int64_t n_seg,
+                   const double* Sn_dev, const double* prefix_dev, mf_precision prec, int32_t p_bands,
+                   const mf_peak* peaks_dev, double* chisq_dev, double* rho_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!bank_dev || !stilde_dev || !Sn_dev || !prefix_dev || !peaks_dev || !chisq_dev)
+        return fail(MF_E_ARG, "null pointer argument");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (p_bands < 2 || p_bands > 64) return fail(MF_E_ARG, "p_bands=%d outside [2, 64]", (int)p_bands);
+    if (n_tmpl < 1 || n_seg < 1 || n_tmpl * n_seg > (int64_t(1) << 31) - 1)
+        return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld", (long long)n_tmpl, (long long)n_seg);
+    hipError_t e = mf::launch_chisq(grid->n, grid->fs, prec, (const mf_bank_entry*)bank_dev, n_tmpl, stilde_dev, n_seg,
+                                    Sn_dev, prefix_dev, p_bands, peaks_dev, chisq_dev, rho_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mf_chisq");
     return ok();
 }
 

@@ -60,13 +60,34 @@ struct FilterArgs {
     void* rho;                // series output
     const void* raw_in;       // mf_ifft input  [units][n]
     void* raw_out;            // mf_ifft output [units][n]
+    // chi^2 band mode (Eq. (5))
+    const int32_t* band_tab;  // [n_tmpl][p_bands + 2]: edges e_0..e_p, index of the transformed band
+    int32_t p_bands;
+    void* qbuf;               // [units][n/2] template x weight product, [k1][k2]
+    void* chi_series;         // chi^2 series output [n_series][n]
 };
+
+// Workspace carve-up of mf_filter_chisq (band mode).
+struct BandLayout {
+    size_t off_w, off_tab, off_q, off_inter, off_part, total;
+    int64_t units_per_batch;
+};
+// the band-mode shape for this N and precision (log2n = -1 if none); units from
+// MF_BAND_UNITS when set
+Plan band_plan(int log2n, mf_precision prec);
+BandLayout band_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg, int p_bands);
 
 // Launchers (return hipError_t of the launch)
 hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
 hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
 hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s);
 hipError_t launch_finalize(const Plan& p, mf_precision prec, const FilterArgs& a, mf_peak* peaks, hipStream_t s);
+
+hipError_t launch_band_table(int64_t n, int n2, const mf_bank_entry* bank, int64_t n_tmpl, const double* prefix,
+                             int p, int32_t* tab, hipStream_t s);
+hipError_t launch_pass1_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s);
+hipError_t launch_pass2_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s);
+hipError_t launch_finalize_band(const Plan& p, const FilterArgs& a, mf_peak* peaks, double* chisq, hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_psd(int64_t n, double fs, double f_low, double f0, int k_lo, double* Sn, hipStream_t s);
@@ -77,6 +98,9 @@ hipError_t launch_sigma(int64_t n, double fs, mf_sigma_mode mode, const double* 
                         int64_t n_tmpl, hipStream_t s);
 hipError_t launch_spa_synth(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
                             void* htilde, hipStream_t s);
+hipError_t launch_chisq(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
+                        const void* stilde, int64_t n_seg, const double* Sn, const double* prefix, int p,
+                        const mf_peak* peaks, double* chisq, double* rho, hipStream_t s);
 hipError_t launch_metric(int64_t n, double fs, int k_lo, const double* theta, const int32_t* khi, int64_t count,
                          const double* Sn, double* metric, hipStream_t s);
 hipError_t launch_snr_grad(int64_t n, double fs, int k_lo, mf_precision prec, const double* theta,

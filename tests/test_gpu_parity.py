@@ -503,3 +503,147 @@ def test_template_metric_matches_oracle(mf):
         ref = O.template_metric(th[i], Sn_ref, n, fs, 40 * 256, kh[i])
         scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
         assert np.max(np.abs(G[i] - ref) / scale) < 1e-9, pairs[i]
+
+
+# ---------------------------------------------------------------------------
+# chi^2 veto of Eq. (5) at each unit's peak
+# ---------------------------------------------------------------------------
+def _chisq_ref(n, fs, mc, eta, s, Sn_ref, j, p):
+    h = O.spa_template(n, fs, 40.0, float(mc), float(eta))
+    k_lo, k_hi = O.band(n, fs, 40.0, float(mc), float(eta))
+    chi2, zl = O.chisq_series(s.astype(np.complex128), Sn_ref, h, n, fs, k_lo, k_hi, p)
+    sig = math.sqrt(O.sigma_sq(h, Sn_ref, fs / n))
+    return float(chi2[j]), float(abs(zl[:, j].sum()) / sig)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ph64"])
+@pytest.mark.parametrize("p", [2, 16])
+def test_chisq_at_peaks_matches_oracle(mf, prec, p):
+    """16-template grid at N=2^16, one SNR-12 injection: chi^2 and rho at every unit's peak."""
+    print(f"[chisq] prec={prec} p={p}", flush=True)
+    n, fs = 1 << 16, 2048.0
+    inj = dict(m1=1.4, m2=1.4, snr=12.0, j0=20011, phi0=0.7)
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    s, Sn_ref = D.segment(n, fs, synth.seed_sequence(11).spawn(1)[0], [inj], dtype=cdt)
+    mc, eta = synth.bank_small_grid()
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    bank = mf.spa_bank(g, mc, eta, Sn, prec)
+    st = torch.from_numpy(s[None]).to(_dev())
+    res = mf.filter(g, bank, st, Sn, prec)
+    chi2, rho = mf.chisq(g, bank, st, Sn, P, res, prec, p_bands=p)
+    chi2, rho = chi2.cpu().numpy(), rho.cpu().numpy()
+    js = res["j"].cpu().numpy()
+    for t in range(len(mc)):
+        c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], s, Sn_ref, int(js[t, 0]), p)
+        assert abs(chi2[t, 0] - c_ref) <= 1e-9 * (c_ref + r_ref ** 2), (t, chi2[t, 0], c_ref)
+        assert rho[t, 0] == pytest.approx(r_ref, rel=1e-10)
+        # the filter's own peak value agrees to its precision class
+        assert float(res["rho"][t, 0]) == pytest.approx(r_ref, rel=1e-9 if prec == "fp64" else 1e-4)
+
+
+def test_chisq_vetoes_a_glitch_full_size(mf):
+    """N=2^20: a loud signal from a far template (a 'glitch' for the bank) gets a large chi^2,
+    a matched injection a chi^2 near its 2p-2 mean; sampled units checked against the oracle."""
+    print("[chisq full]", flush=True)
+    n, fs, p = 1 << 20, 4096.0, 16
+    injs = [[dict(m1=1.4, m2=1.4, snr=15.0, j0=300007, phi0=1.1)],
+            [dict(m1=6.0, m2=1.1, snr=80.0, j0=700001, phi0=2.3)]]
+    segs = []
+    for i, inj in enumerate(injs):
+        s, Sn_ref = D.segment(n, fs, synth.seed_sequence(12).spawn(2)[i], inj, dtype=np.complex64)
+        segs.append(s)
+    mc = np.array([float(synth.mc_eta(1.4, 1.4)[0]), float(synth.mc_eta(1.6, 1.6)[0])])
+    eta = np.array([0.25, 0.25])
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
+    st = torch.from_numpy(np.stack(segs)).to(_dev())
+    res = mf.filter(g, bank, st, Sn, "fp32_ph64")
+    chi2, rho = mf.chisq(g, bank, st, Sn, P, res, "fp32_ph64", p_bands=p)
+    chi2 = chi2.cpu().numpy()
+    js = res["j"].cpu().numpy()
+    assert chi2[0, 0] < 2.5 * (2 * p - 2)          # matched template on the matched injection
+    assert chi2[0, 1] > 5.0 * (2 * p - 2)          # the loud mismatched signal
+    for t, sgi in [(0, 0), (1, 1)]:
+        c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], segs[sgi], Sn_ref, int(js[t, sgi]), p)
+        assert abs(chi2[t, sgi] - c_ref) <= 1e-9 * (c_ref + r_ref ** 2)
+
+
+# ---------------------------------------------------------------------------
+# chi^2 over the whole series (band mode of the filter)
+# ---------------------------------------------------------------------------
+def _band_bank():
+    """Templates from 1+1 to 30+5 M_sun: the transformed band and the row span of the others vary."""
+    pairs = [(1.0, 1.0), (1.4, 1.4), (2.0, 1.2), (3.0, 3.0), (5.0, 1.5), (8.0, 8.0), (12.0, 3.0), (30.0, 5.0)]
+    mc, eta = zip(*[tuple(map(float, synth.mc_eta(a, b))) for a, b in pairs])
+    return np.array(mc), np.array(eta)
+
+
+@pytest.mark.parametrize("prec,p,units", [("fp64", 16, None), ("fp32_ph64", 16, None), ("fp32_ph64", 2, None),
+                                          ("fp64", 5, "3"), ("fp32_ph64", 64, "5")])
+def test_filter_chisq_series_matches_oracle(mf, prec, p, units):
+    """N=2^14 at 1024 Hz, 8 templates x 2 segments (one injection each): chi^2 and rho series of every unit."""
+    print(f"[filter_chisq series] prec={prec} p={p} units={units}", flush=True)
+    n, fs = 1 << 14, 1024.0
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    segs = []
+    injs = [dict(m1=1.4, m2=1.4, snr=14.0, j0=5003, phi0=0.3), dict(m1=8.0, m2=8.0, snr=25.0, j0=12001, phi0=2.0)]
+    for i, inj in enumerate(injs):
+        s, Sn_ref = D.segment(n, fs, synth.seed_sequence(13).spawn(2)[i], [inj], dtype=cdt)
+        segs.append(s)
+    mc, eta = _band_bank()
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    bank = mf.spa_bank(g, mc, eta, Sn, prec)
+    st = torch.from_numpy(np.stack(segs)).to(_dev())
+    n_units = len(mc) * 2
+    res = _with_env({"MF_BAND_UNITS": units} if units else {},
+                    lambda: mf.filter_chisq(g, bank, st, Sn, P, prec, p_bands=p, series_units=list(range(n_units))))
+    chi_s = res["chisq_series"].cpu().numpy().astype(np.float64)
+    rho_s = res["series"].cpu().numpy().astype(np.float64)
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    for t in range(len(mc)):
+        h = O.spa_template(n, fs, 40.0, float(mc[t]), float(eta[t]))
+        k_lo, k_hi = O.band(n, fs, 40.0, float(mc[t]), float(eta[t]))
+        sig = math.sqrt(O.sigma_sq(h, Sn_ref, fs / n))
+        for s_i in range(2):
+            chi_ref, zl = O.chisq_series(segs[s_i].astype(np.complex128), Sn_ref, h, n, fs, k_lo, k_hi, p)
+            rho_ref = np.abs(zl.sum(0)) / sig
+            u = t * 2 + s_i
+            scale = chi_ref + rho_ref ** 2 + 1.0
+            err = np.max(np.abs(chi_s[u] - chi_ref) / scale)
+            assert err < tol, (t, s_i, err)
+            assert D.series_error(rho_s[u], rho_ref) < (1e-10 if prec == "fp64" else 1e-4)
+            j = int(res["j"][t, s_i])
+            assert D.peak_index_ok(j, rho_ref, int(np.argmax(rho_ref)), rel=1e-9 if prec == "fp64" else 2e-4)
+            assert float(res["chisq"][t, s_i]) == pytest.approx(chi_s[u, j], rel=1e-6, abs=1e-6)
+
+
+def test_filter_chisq_agrees_with_filter_and_point_chisq_full_size(mf):
+    """N=2^20, uneven 24-template bank x 2 segments, FP64: peaks equal mf_filter's, and chi^2 at the
+    peaks equals the direct per-peak evaluation (mf_chisq); two units checked against the oracle."""
+    print("[filter_chisq full]", flush=True)
+    n, fs, p = 1 << 20, 4096.0, 16
+    rng = synth.rngs(14, 1)[0]
+    mc, eta, _, _ = synth.bank_uneven(24, rng)
+    segs = []
+    injs = [dict(m1=1.5, m2=1.3, snr=12.0, j0=200003, phi0=0.4), dict(m1=6.0, m2=1.1, snr=60.0, j0=800011, phi0=1.9)]
+    for i, inj in enumerate(injs):
+        s, Sn_ref = D.segment(n, fs, synth.seed_sequence(14).spawn(2)[i], [inj], dtype=np.complex128)
+        segs.append(s)
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp64")
+    st = torch.from_numpy(np.stack(segs)).to(_dev())
+    res = mf.filter_chisq(g, bank, st, Sn, P, "fp64", p_bands=p, threshold=6.0)
+    plain = mf.filter(g, bank, st, Sn, "fp64", threshold=6.0)
+    assert torch.equal(res["j"], plain["j"])
+    assert torch.equal(res["n_above"], plain["n_above"])
+    assert torch.allclose(res["rho"], plain["rho"], rtol=1e-10, atol=0)
+    chi_pt, rho_pt = mf.chisq(g, bank, st, Sn, P, res, "fp64", p_bands=p)
+    scale = chi_pt + rho_pt ** 2 + 1.0
+    assert float(((res["chisq"] - chi_pt).abs() / scale).max()) < 1e-9
+    for t, s_i in [(0, 0), (len(mc) - 1, 1)]:
+        c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], segs[s_i], Sn_ref, int(res["j"][t, s_i]), p)
+        assert abs(float(res["chisq"][t, s_i]) - c_ref) <= 1e-9 * (c_ref + r_ref ** 2 + 1.0)

@@ -425,3 +425,85 @@ def test_template_metric_predicts_the_quadratic_falloff():
         F = O.snr_sq((mc + dlt[0], eta + dlt[1], t0 + dlt[2]), s, Sn, n, fs, k_lo, k_hi)[0]
         pred = dlt @ g @ dlt
         assert 1.0 - F / Fs == pytest.approx(pred, rel=2e-2), direction
+
+
+# ---------------------------------------------------------------------------
+# Eq. (5): chi^2 veto
+# ---------------------------------------------------------------------------
+def _chisq_case(noise, snr=12.0, j0=7000, m=(1.4, 1.4), seed=41):
+    n, fs = 1 << 14, 1024.0
+    mc, eta = map(float, synth.mc_eta(*m))
+    if noise:
+        s, Sn, g = _noise_segment(n, fs, seed, injection=(mc, eta, snr, j0, 0.3) if snr else None)
+    else:
+        g = O.grid(n, fs)
+        Sn = O.psd_bins(n, fs, 40.0)
+        h = O.spa_template(n, fs, 40.0, mc, eta)
+        sig = math.sqrt(O.sigma_sq(h, Sn, g["df"]))
+        s = synth.inject(np.zeros(n // 2 + 1, complex), h, snr / sig, 0.3, j0, n)
+    h = O.spa_template(n, fs, 40.0, mc, eta)
+    k_lo, k_hi = O.band(n, fs, 40.0, mc, eta)
+    return n, fs, s, Sn, g, h, k_lo, k_hi
+
+
+def test_chisq_band_edges_split_sigma_equally():
+    n, fs, s, Sn, g, h, k_lo, k_hi = _chisq_case(noise=False)
+    for p in (2, 4, 16):
+        e = O.chisq_band_edges(Sn, n, fs, k_lo, k_hi, p)
+        assert e[0] == k_lo and e[-1] == k_hi + 1 and np.all(np.diff(e) > 0)
+        f = O.freqs(n, fs)
+        W = np.zeros(n // 2 + 1)
+        W[k_lo: k_hi + 1] = f[k_lo: k_hi + 1] ** (-7.0 / 3.0) / Sn[k_lo: k_hi + 1]
+        shares = np.array([W[e[l]: e[l + 1]].sum() for l in range(p)]) / W.sum()
+        # each band's share is 1/p up to one bin's weight
+        assert np.all(np.abs(shares - 1.0 / p) <= W.max() / W.sum() + 1e-15)
+
+
+def test_chisq_noiseless_injection_closed_form():
+    # s = A e^{i phi} h shifted to j0: z_l(j0) = A e^{i phi} sigma_l^2, so
+    # chi^2(j0) = p A^2 / sigma^2 sum_l (sigma_l^2 - sigma^2 / p)^2 (~0: equal bands).
+    p = 16
+    n, fs, s, Sn, g, h, k_lo, k_hi = _chisq_case(noise=False)
+    chi2, zl = O.chisq_series(s, Sn, h, n, fs, k_lo, k_hi, p)
+    e = O.chisq_band_edges(Sn, n, fs, k_lo, k_hi, p)
+    inv = np.where(np.isfinite(Sn), 1.0 / Sn, 0.0)
+    sl2 = np.array([4 * g["df"] * np.sum(np.abs(h[e[l]: e[l + 1]]) ** 2 * inv[e[l]: e[l + 1]]) for l in range(p)])
+    s2 = sl2.sum()
+    A = 12.0 / math.sqrt(s2)
+    closed = p * A * A / s2 * np.sum((sl2 - s2 / p) ** 2)
+    assert chi2[7000] == pytest.approx(closed, rel=1e-9, abs=1e-12)
+    assert chi2[7000] < 1e-3
+    np.testing.assert_allclose(np.abs(zl[:, 7000]), A * sl2, rtol=1e-10)
+
+
+def test_chisq_bands_sum_to_filter_output():
+    n, fs, s, Sn, g, h, k_lo, k_hi = _chisq_case(noise=True)
+    chi2, zl = O.chisq_series(s, Sn, h, n, fs, k_lo, k_hi, 8)
+    z = O.filter_z(s, Sn, h, n, g["df"])
+    np.testing.assert_allclose(zl.sum(axis=0), z, atol=1e-12 * np.abs(z).max())
+
+
+def test_chisq_noise_mean_is_2p_minus_2():
+    # Sec. 1.2: in stationary Gaussian noise chi^2 has nu = 2p - 2 degrees of freedom.
+    p = 16
+    vals = []
+    for seed in range(6):
+        n, fs, s, Sn, g, h, k_lo, k_hi = _chisq_case(noise=True, snr=0.0, seed=300 + seed)
+        chi2, _ = O.chisq_series(s, Sn, h, n, fs, k_lo, k_hi, p)
+        vals.append(chi2.mean())
+    assert np.mean(vals) == pytest.approx(2 * p - 2, rel=0.03)
+
+
+def test_chisq_flags_a_mismatched_glitch():
+    # A loud signal that is a poor match (another template) leaves a large chi^2
+    # at the peak of the filter output, while a matched signal does not.
+    p = 16
+    n, fs, s, Sn, g, h, k_lo, k_hi = _chisq_case(noise=True, snr=0.0, seed=77)
+    mc2, eta2 = map(float, synth.mc_eta(6.0, 1.1))
+    h2 = O.spa_template(n, fs, 40.0, mc2, eta2)
+    glitch = synth.inject(s, h2, 80.0 / math.sqrt(O.sigma_sq(h2, Sn, g["df"])), 0.0, 5000, n)
+    matched = synth.inject(s, h, 80.0 / math.sqrt(O.sigma_sq(h, Sn, g["df"])), 0.0, 5000, n)
+    chi2, zl = O.chisq_series(glitch, Sn, h, n, fs, k_lo, k_hi, p)
+    assert chi2[int(np.argmax(np.abs(zl.sum(axis=0))))] > 5 * (2 * p - 2)
+    chi2, zl = O.chisq_series(matched, Sn, h, n, fs, k_lo, k_hi, p)
+    assert chi2[int(np.argmax(np.abs(zl.sum(axis=0))))] < 2 * (2 * p - 2)
