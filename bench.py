@@ -35,7 +35,8 @@ METRIC = "templates×segments/s at 2^20-pt IFFT; HBM GB/s fraction; vs FP64 path
 UNIT = "templates×segments/s"
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f) for f in ("k_filter.hip", "mf_device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f)
+                  for f in ("k_filter.hip", "k_filter_chisq.hip", "filter_tiles.hpp", "mf_device.hpp")]
 
 
 def kernel_hash() -> str:
@@ -188,11 +189,43 @@ def run_gpu(args):
                "b_alg_unit": float(np.mean(b * n_act + 2 * b * wl.n + 16))}
         return out
 
+    def measure_chisq(prec: str, steps: int, warmup: int, stride: int, p_bands: int):
+        """Band mode: the filter plus chi^2 (Eq. (5)) at every sample of every unit."""
+        import ctypes as C
+        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        _, P = mf.psd(grid, prefix=True, device=dev)
+        st = S64 if prec == "fp64" else S32
+        ws = torch.empty(mf.filter_chisq_workspace_bytes(grid, prec, bank.n_tmpl, n_seg, p_bands),
+                         dtype=torch.uint8, device=dev)
+        for _ in range(warmup):
+            res = mf.filter_chisq(grid, bank, st, Sn, P, prec, p_bands=p_bands, workspace=ws)
+        torch.cuda.synchronize()
+        lib = L.load()
+        lib.mf_timing_enable(stride)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = mf.filter_chisq(grid, bank, st, Sn, P, prec, p_bands=p_bands, workspace=ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, nl, u1, u2 = (C.c_double * 3)(), (C.c_int64 * 3)(), (C.c_int64 * 3)(), (C.c_int64 * 3)()
+        L.check(lib.mf_timing_read_split(ms, nl, u1, u2))
+        lib.mf_timing_enable(0)
+        units = bank.n_tmpl * n_seg
+        chi = res["chisq"].cpu().numpy()
+        return {"prec": prec, "p_bands": p_bands, "ms_per_step": 1e3 * wall / steps, "steps": steps, "units": units,
+                "plan": mf.filter_chisq_plan(grid, prec),
+                "pass2": {"ms": ms[1], "launches": nl[1], "units": u2[1]},
+                "pass1": {"ms": ms[0], "launches": nl[0], "units": u1[0]},
+                "chisq_at_peaks_median": float(np.median(chi))}
+
     main = measure(args.precision, args.steps, args.warmup, args.timing_stride)
     fp64 = None
     if args.fp64_steps > 0:
         fp64 = measure("fp64", args.fp64_steps, 1, args.timing_stride)
-    return main, fp64
+    chisq = None
+    if args.chisq_steps > 0:
+        chisq = measure_chisq(args.precision, args.chisq_steps, 1, args.timing_stride, args.chisq_bands)
+    return main, fp64, chisq
 
 
 def run_refine(args):
@@ -287,6 +320,31 @@ def roofline(m, workload_name: str, khash: str):
     return rec
 
 
+FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 2.4 GHz x 64 lanes x 2 (FMA); packed FP32 is not used
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def chisq_roofline(c, wl, khash: str):
+    """Roofline record of the band-mode pass 2 (the chi^2 path's dominant kernel): p row
+    transforms of N2 points for each of the N1 rows, counted as 5 N2 log2 N2 flops each."""
+    k = c["pass2"]
+    if k["launches"] == 0 or k["ms"] <= 0:
+        return None
+    n1, n2 = c["plan"]["n1"], c["plan"]["n2"]
+    flops_unit = c["p_bands"] * n1 * 5.0 * n2 * math.log2(n2)
+    avg_ms = k["ms"] / k["launches"]
+    units_per_launch = k["units"] / k["launches"]
+    ach = flops_unit * units_per_launch / (avg_ms * 1e-3) / 1e12
+    peak = FP64_VALU_PEAK_TFLOPS if c["prec"] == "fp64" else FP32_VALU_PEAK_TFLOPS
+    prec = "fp64" if c["prec"] == "fp64" else "fp32"
+    name = f"k_pass2_band_{prec}"
+    tb = read_traffic(name, wl.name, khash)
+    return {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+            "traffic": round(tb) if tb is not None else None, "kernel": name, "avg_launch_ms": round(avg_ms, 4),
+            "units_per_launch": round(units_per_launch, 2), "flops_per_unit": flops_unit,
+            "launches_timed": k["launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +358,8 @@ def main():
     ap.add_argument("--cpu-procs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine-steps", type=int, default=20)
+    ap.add_argument("--chisq-steps", type=int, default=5)
+    ap.add_argument("--chisq-bands", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -317,7 +377,7 @@ def main():
         print(f"[bench] cpu baseline {cpu['value']:.2f} {UNIT} on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     print(f"[bench] gpu workload {wl.name} precision {args.precision}", file=sys.stderr, flush=True)
-    m, fp64 = run_gpu(args)
+    m, fp64, chisq = run_gpu(args)
     khash = kernel_hash()
     value = m["units"] / (m["ms_per_step"] * 1e-3)
     eff_gbs = m["b_alg_unit"] * m["units"] / (m["ms_per_step"] * 1e-3) / 1e9
@@ -344,6 +404,16 @@ def main():
                              "steps": fp64["steps"], "effective_hbm_frac": round(e64 / HBM_PEAK_GBS, 4),
                              "roofline": roofline(fp64, wl.name, khash),
                              "speedup_fp32_over_fp64": round(value / v64, 3)}
+    if chisq is not None:
+        vc = chisq["units"] / (chisq["ms_per_step"] * 1e-3)
+        line["chisq_path"] = {
+            "value": round(vc, 1), "unit": UNIT, "p_bands": chisq["p_bands"],
+            "ms_per_step": round(chisq["ms_per_step"], 4), "steps": chisq["steps"],
+            "us_per_unit": round(chisq["ms_per_step"] * 1e3 / chisq["units"], 3),
+            "slowdown_vs_filter": round(value / vc, 3),
+            "chisq_at_peaks_median": round(chisq["chisq_at_peaks_median"], 3),
+            "plan": chisq["plan"],
+            "roofline": chisq_roofline(chisq, wl, khash)}
     print(json.dumps(line), flush=True)
 
 

@@ -86,6 +86,14 @@ typedef struct {
     int32_t n_above;
 } mf_peak;
 
+/* One event (Sec. 3.3: triggers carry their SNR and chi^2): rho at sample j
+ * of template t.  t = -1 marks a window without an event. */
+typedef struct {
+    double rho;
+    int32_t j;
+    int32_t t;
+} mf_event;
+
 /* Options of mf_filter.  A NULL options pointer means: no threshold count
  * (rho_threshold = +inf), window = the whole segment, no series. */
 typedef struct {
@@ -150,6 +158,35 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
  */
 mf_status mf_psd(const mf_grid* grid, double* Sn_dev, double* prefix_dev,
                  mf_stream_t stream);
+
+/*
+ * mf_psd_prefix -- the prefix array of mf_psd for a caller-supplied PSD
+ * (setup call).  Any one-sided S_n array [N/2+1] can be passed to the other
+ * calls in place of mf_psd's: they read it only on [k_lo, N/2-1] (bins
+ * outside count as 1/S_n = 0, reading R3) and it must be finite and > 0
+ * there (not checked on the device: a bad value propagates as NaN/inf into
+ * sigma and rho).  This call writes P_k = sum_{1<=k'<=k, S finite}
+ * f_k'^(-7/3) / S_n,k' for the chi^2 band edges.
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_BAND, MF_E_HIP.
+ */
+mf_status mf_psd_prefix(const mf_grid* grid, const double* Sn_dev, double* prefix_dev,
+                        mf_stream_t stream);
+
+/*
+ * mf_rfft_workspace_bytes / mf_rfft -- one-sided spectra of real time-domain
+ * segments, s_k = dt sum_j x_j e^{-2 pi i jk/N} for k = 0..N/2 (the
+ * discretisation of Eq. (1), reading R8; the paper's forward data FFTs,
+ * Sec. 3.1).
+ *   x_dev      [batch][N] real (double for MF_FP64, float otherwise).
+ *   stilde_dev [batch][N/2+1] complex (complex128 / complex64), written: the
+ *              layout mf_filter takes.
+ *   N a power of two in [2^11, 2^23]; fs > 0 (dt = 1/fs).
+ *   workspace  >= mf_rfft_workspace_bytes(n, prec, batch), 256-byte aligned.
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_WORKSPACE, MF_E_HIP.
+ */
+size_t mf_rfft_workspace_bytes(int64_t n, mf_precision prec, int64_t batch);
+mf_status mf_rfft(int64_t n, double fs, mf_precision prec, const void* x_dev, void* stilde_dev,
+                  int64_t batch, void* workspace_dev, size_t workspace_bytes, mf_stream_t stream);
 
 /*
  * mf_spa_bank -- 2PN stationary-phase templates (Sec. 1.1) and their norm
@@ -228,6 +265,52 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
                       const double* gbar_dev, double* grad_dev, mf_stream_t stream);
 
 /*
+ * mf_filter_events_workspace_bytes / mf_filter_events -- mf_filter with
+ * thresholded, clustered events (Sec. 3.3; the paper gives no rule, this is
+ * the library's): each series is cut into windows of W = 2^log2_window
+ * samples.
+ *  * Time clustering per (template, segment): a window's winner is its
+ *    loudest sample with rho >= rho_threshold (lowest index on ties); it is an
+ *    event unless the winner of an adjacent window lies within W samples of it
+ *    with a larger rho (or an equal rho at a lower index).
+ *  * Template clustering per segment: each window's loudest event across
+ *    templates (ties: lowest template index), kept under the same rule.
+ *   Arguments as for mf_filter (whole series, no window or series options),
+ *   plus:
+ *   rho_threshold   > 0; peaks_dev[].n_above counts samples at or above it.
+ *   log2_window     4 <= log2_window <= min(16, log2 N).
+ *   workspace       >= mf_filter_events_workspace_bytes(...), 256-byte aligned.
+ *   unit_events_dev nullable [n_tmpl][n_seg][N/W] mf_event: time-clustered
+ *                   events of every unit (t = -1 where none).
+ *   seg_events_dev  [n_seg][N/W] mf_event, written: the segment events.
+ * In MF_FP64 the window winner is decided on |z|^2 rounded down to 36
+ * mantissa bits (relative 1.5e-11).
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_WORKSPACE, MF_E_HIP.
+ */
+size_t mf_filter_events_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl,
+                                        int64_t n_seg, int32_t log2_window);
+mf_status mf_filter_events(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
+                           const void* stilde_dev, int64_t n_seg, const double* Sn_dev,
+                           mf_precision prec, double rho_threshold, int32_t log2_window,
+                           void* workspace_dev, size_t workspace_bytes, mf_peak* peaks_dev,
+                           mf_event* unit_events_dev, mf_event* seg_events_dev, mf_stream_t stream);
+
+/*
+ * mf_chisq_events -- chi^2 of Eq. (5) and rho at listed events (hot call),
+ * as mf_chisq but for event records instead of unit peaks.
+ *   events_dev [n_seg][n_per_seg] mf_event (e.g. the seg_events_dev of
+ *              mf_filter_events); row s belongs to segment s; entries with
+ *              t < 0 are skipped (outputs 0).
+ *   chisq_dev, rho_dev (nullable) [n_seg][n_per_seg] double, written.
+ * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_BAND, MF_E_HIP.
+ */
+mf_status mf_chisq_events(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
+                          const void* stilde_dev, int64_t n_seg, const double* Sn_dev,
+                          const double* prefix_dev, mf_precision prec, int32_t p_bands,
+                          const mf_event* events_dev, int64_t n_per_seg, double* chisq_dev,
+                          double* rho_dev, mf_stream_t stream);
+
+/*
  * mf_filter_chisq_workspace_bytes -- device workspace mf_filter_chisq needs:
  * the weighted data, the band table, and per batch of units the template x
  * weight product [N/2] and one intermediate [N], plus peak partials.  0 for
@@ -235,6 +318,11 @@ mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_
  */
 size_t mf_filter_chisq_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl,
                                        int64_t n_seg, int32_t p_bands);
+
+/* The launch plan of mf_filter_chisq for this grid and precision (layout of
+ * mf_filter_plan; the last entry is 0).  Errors: MF_E_ARG, MF_E_SHAPE,
+ * MF_E_UNSUPPORTED. */
+mf_status mf_filter_chisq_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 
 /*
  * mf_filter_chisq -- the matched filter of mf_filter with the chi^2
@@ -308,6 +396,11 @@ mf_status mf_template_metric(const mf_grid* grid, const double* theta_dev, const
  */
 mf_status mf_timing_enable(int32_t stride);
 mf_status mf_timing_read(double* ms, int64_t* launches, int64_t* pass1_units, int64_t* pass2_units);
+/* The same record split by launch kind: [0] pass-1 launches, [1] pass-2
+ * launches, [2] pipelined steps (both roles).  mf_filter_chisq records its
+ * band-mode passes the same way. */
+mf_status mf_timing_read_split(double ms[3], int64_t launches[3], int64_t pass1_units[3],
+                               int64_t pass2_units[3]);
 
 /*
  * Calibration kernel (not part of the method): copies `bytes` (a non-zero

@@ -46,6 +46,13 @@ R13 Gradient of rho^2 w.r.t. (M_c, eta, t_c): the band K is frozen at the
 R16 chi^2 bands (Eq. (5), Sec. 1.2): p contiguous bands of the template's
     band with equal shares of sigma^2; a bin belongs to the band in which the
     W-sum of the bins before it falls (W_k = f_k^(-7/3) / S_k).
+R17 Events (Sec. 3.3 names events with their SNR and chi^2 but gives no
+    threshold or clustering rule): the series is cut into windows of W
+    samples; a window's winner is its maximum of rho (lowest index on ties);
+    it is an event if rho >= rho_th and the winner of neither adjacent window
+    lies within W samples of it with a larger rho (or an equal rho at a lower
+    index).  Across the templates of one segment the same rule runs on the
+    loudest unit event of each window (ties: lowest template index).
 """
 from __future__ import annotations
 
@@ -92,6 +99,39 @@ def psd_bins(n: int, fs: float, f_low: float, f0: float = PSD_F0) -> np.ndarray:
     f = freqs(n, fs)
     S[k_lo: n // 2] = psd_initial_ligo(f[k_lo: n // 2], f0)
     return S
+
+
+def psd_from_array(S_user, n: int, fs: float, f_low: float) -> np.ndarray:
+    """A caller-supplied one-sided PSD on the bins, restricted to the band (R3):
+    S_k inside [k_lo, N/2-1], +inf elsewhere, so that 1/S_k = 0 outside."""
+    S_user = np.asarray(S_user, dtype=np.float64)
+    if S_user.shape != (n // 2 + 1,):
+        raise ValueError("PSD must have N/2+1 one-sided bins")
+    k_lo = band_lo(n, fs, f_low)
+    S = np.full(n // 2 + 1, np.inf)
+    S[k_lo: n // 2] = S_user[k_lo: n // 2]
+    return S
+
+
+def prefix_sums(Sn: np.ndarray, n: int, fs: float) -> np.ndarray:
+    """P_k = sum_{1 <= k' <= k} f_k'^(-7/3) / S_k' over the bins where S is finite:
+    the running form of the Eq. (4) sum, so sigma^2 of a template on
+    [k_lo, k_hi] is 4 df (P[k_hi] - P[k_lo - 1])."""
+    f = freqs(n, fs)
+    W = np.zeros(n // 2 + 1)
+    ok = np.isfinite(Sn)
+    ok[0] = False
+    W[ok] = f[ok] ** (-7.0 / 3.0) / Sn[ok]
+    return np.cumsum(W)
+
+
+# ---------------------------------------------------------------------------
+# Time-domain input (reading R8): one-sided spectrum of a real segment
+# ---------------------------------------------------------------------------
+def segment_spectrum(x: np.ndarray, fs: float) -> np.ndarray:
+    """s_k = dt sum_j x_j e^{-2 pi i jk/N} for k = 0..N/2 (R8) of a real segment x[N]."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.fft.rfft(x) / fs
 
 
 # ---------------------------------------------------------------------------
@@ -283,6 +323,67 @@ def chisq_series(stilde: np.ndarray, Sn: np.ndarray, htilde: np.ndarray, n: int,
 
 
 # ---------------------------------------------------------------------------
+# Events: threshold and clustering of rho(t) (Sec. 3.3; reading R17)
+# ---------------------------------------------------------------------------
+def window_maxima(rho: np.ndarray, W: int):
+    """Index and value of the maximum of rho in each window [wW, (w+1)W) (lowest index on ties)."""
+    n = rho.shape[0]
+    nwin = n // W
+    js = np.empty(nwin, dtype=np.int64)
+    vals = np.empty(nwin)
+    for w in range(nwin):
+        seg = rho[w * W: (w + 1) * W]
+        i = int(np.argmax(seg))  # first occurrence of the maximum
+        js[w] = w * W + i
+        vals[w] = seg[i]
+    return js, vals
+
+
+def _keep_window_winners(js, vals, threshold: float, W: int):
+    """Windows whose winner reaches the threshold and is not beaten by the winner of an
+    adjacent window lying within W samples of it (larger value, or equal value at a lower index)."""
+    keep = []
+    nwin = len(js)
+    for w in range(nwin):
+        j, v = int(js[w]), float(vals[w])
+        if not v >= threshold:
+            continue
+        beaten = False
+        for w2 in (w - 1, w + 1):
+            if 0 <= w2 < nwin and abs(int(js[w2]) - j) <= W:
+                v2, j2 = float(vals[w2]), int(js[w2])
+                if v2 > v or (v2 == v and j2 < j):
+                    beaten = True
+        if not beaten:
+            keep.append(w)
+    return keep
+
+
+def unit_events(rho: np.ndarray, threshold: float, W: int):
+    """Events of one (template, segment) rho series (R17): [(window, j, rho)], time-ordered."""
+    js, vals = window_maxima(rho, W)
+    return [(w, int(js[w]), float(vals[w])) for w in _keep_window_winners(js, vals, threshold, W)]
+
+
+def segment_events(events_by_template: dict, n: int, threshold: float, W: int):
+    """Events of one segment across templates (R17): in each window the loudest unit event
+    (ties: lowest template index), kept under the same adjacent-window rule.
+    events_by_template: {t: unit_events(...)}; returns [(window, t, j, rho)]."""
+    nwin = n // W
+    best_t = np.full(nwin, -1, dtype=np.int64)
+    best_j = np.zeros(nwin, dtype=np.int64)
+    best_v = np.full(nwin, -np.inf)
+    for t in sorted(events_by_template):
+        for (w, j, v) in events_by_template[t]:
+            if v > best_v[w]:  # strict: an equal value keeps the lower template index
+                best_t[w], best_j[w], best_v[w] = t, j, v
+    occupied = best_t >= 0
+    js = np.where(occupied, best_j, np.arange(nwin) * W)
+    keep = _keep_window_winners(js, best_v, threshold, W)
+    return [(w, int(best_t[w]), int(best_j[w]), float(best_v[w])) for w in keep if occupied[w]]
+
+
+# ---------------------------------------------------------------------------
 # Gradient of rho^2 with respect to (M_c, eta, t_c)  (reading R13)
 # ---------------------------------------------------------------------------
 def _spa_phase_and_partials(f: np.ndarray, mc: float, eta: float, tc: float):
@@ -381,6 +482,8 @@ def naive_dft(x: np.ndarray, sign: int = +1) -> np.ndarray:
 
 
 __all__ = [
+    "window_maxima", "unit_events", "segment_events",
+    "psd_from_array", "prefix_sums", "segment_spectrum",
     "T_SUN", "PSD_F0", "grid", "freqs", "psd_initial_ligo", "psd_bins",
     "total_mass_from_mc_eta", "f_isco", "band_lo", "band", "spa_phase",
     "spa_amplitude", "spa_template", "quadrature_partner", "sigma_sq",

@@ -25,7 +25,8 @@ from . import _lib as L
 
 __all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_plan", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
            "PRECISIONS", "version",
-           "template_metric", "chisq", "filter_chisq", "filter_chisq_workspace_bytes"]
+           "template_metric", "chisq", "filter_chisq", "filter_chisq_workspace_bytes",
+           "psd_prefix", "rfft", "filter_events", "chisq_events", "filter_chisq_plan"]
 
 PRECISIONS = {"fp64": L.MF_FP64, "fp32_ph64": L.MF_FP32_PH64, "fp32": L.MF_FP32}
 SIGMA_MODES = {"fp64": L.MF_SIGMA_FP64, "comp32": L.MF_SIGMA_COMP32}
@@ -147,6 +148,15 @@ def filter_plan(grid: Grid, precision="fp32_ph64") -> dict:
     return dict(zip(keys, [int(x) for x in arr]))
 
 
+def filter_chisq_plan(grid: Grid, precision="fp32_ph64") -> dict:
+    """The launch plan mf_filter_chisq uses for this grid and precision."""
+    arr = (C.c_int32 * 8)()
+    g = grid.c()
+    L.check(_clib.mf_filter_chisq_plan(C.byref(g), _prec(precision), arr))
+    keys = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "fused")
+    return dict(zip(keys, [int(x) for x in arr]))
+
+
 _tune_cache_loaded = False
 
 
@@ -257,6 +267,102 @@ def filter_chisq(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor,
     ints = pk[..., 1].contiguous().view(torch.int32).view(bank.n_tmpl, n_seg, 2)
     return {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "series": series, "raw": peaks,
             "chisq": chisq, "chisq_series": chi_series}
+
+
+def psd_prefix(grid: Grid, Sn: torch.Tensor) -> torch.Tensor:
+    """Prefix array (the chi^2 band edges' sums) of a caller-supplied PSD [N/2+1] on the GPU."""
+    _require_cuda(Sn)
+    if Sn.dtype != torch.float64 or not Sn.is_contiguous() or Sn.numel() != grid.n // 2 + 1:
+        raise ValueError(f"Sn must be contiguous float64 of {grid.n // 2 + 1} bins")
+    P = torch.empty_like(Sn)
+    g = grid.c()
+    L.check(_clib.mf_psd_prefix(C.byref(g), _ptr(Sn), _ptr(P), _stream(Sn.device)))
+    return P
+
+
+def rfft(x: torch.Tensor, fs: float, precision="fp32_ph64", workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """One-sided spectra s_k = dt sum_j x_j e^{-2 pi i jk/N}, k = 0..N/2, of real segments x [..., N]."""
+    prec = _prec(precision)
+    _require_cuda(x)
+    want = torch.float64 if prec == L.MF_FP64 else torch.float32
+    if x.dtype != want or not x.is_contiguous():
+        raise ValueError(f"x must be contiguous {want}")
+    n = int(x.shape[-1])
+    batch = int(x.numel() // n)
+    need = int(_clib.mf_rfft_workspace_bytes(n, prec, batch))
+    if need == 0:
+        raise L.MfError(-2, _clib.mf_last_error().decode())
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    out = torch.empty(tuple(x.shape[:-1]) + (n // 2 + 1,), dtype=_cdtype(prec), device=x.device)
+    L.check(_clib.mf_rfft(n, float(fs), prec, _ptr(x), _ptr(out), batch, _ptr(workspace), workspace.numel(),
+                          _stream(x.device)))
+    return out
+
+
+def _events_view(raw: torch.Tensor, shape):
+    """(rho float64, j int32, t int32) views of an mf_event buffer (16 bytes per record)."""
+    ev = raw.view(*shape, 2)
+    ints = ev[..., 1].contiguous().view(torch.int32).view(*shape, 2)
+    return {"rho": ev[..., 0], "j": ints[..., 0], "t": ints[..., 1], "raw": raw}
+
+
+def filter_events(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, precision="fp32_ph64",
+                  threshold: float = 5.5, log2_window: int = 12, unit_events: bool = False,
+                  workspace: torch.Tensor | None = None):
+    """:func:`filter` plus thresholded, clustered events in windows of 2^log2_window samples.
+
+    Returns the dict of :func:`filter` plus "seg_events" ({rho, j, t} of shape
+    [n_seg, N >> log2_window]; t = -1 where a window has no event) and, with
+    unit_events=True, "unit_events" of shape [n_tmpl, n_seg, N >> log2_window].
+    """
+    prec = _prec(precision)
+    _require_cuda(stilde, Sn)
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous() or stilde.shape[-1] != grid.n // 2 + 1:
+        raise ValueError(f"stilde must be contiguous {_cdtype(prec)} of shape [n_seg, {grid.n // 2 + 1}]")
+    n_seg = int(stilde.shape[0])
+    dev = stilde.device
+    g = grid.c()
+    need = int(_clib.mf_filter_events_workspace_bytes(C.byref(g), prec, bank.n_tmpl, n_seg, int(log2_window)))
+    if need == 0:
+        raise L.MfError(-1, "no events workspace for these arguments (log2_window in [4, min(16, log2 N)])")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    n_win = grid.n >> int(log2_window)
+    peaks = torch.empty(2 * bank.n_tmpl * n_seg, dtype=torch.float64, device=dev)
+    seg = torch.empty(2 * n_seg * n_win, dtype=torch.float64, device=dev)
+    unit = torch.empty(2 * bank.n_tmpl * n_seg * n_win, dtype=torch.float64, device=dev) if unit_events else None
+    L.check(_clib.mf_filter_events(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn), prec,
+                                   float(threshold), int(log2_window), _ptr(workspace), workspace.numel(),
+                                   _ptr(peaks), _ptr(unit), _ptr(seg), _stream(dev)))
+    pk = peaks.view(bank.n_tmpl, n_seg, 2)
+    ints = pk[..., 1].contiguous().view(torch.int32).view(bank.n_tmpl, n_seg, 2)
+    out = {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "raw": peaks,
+           "seg_events": _events_view(seg, (n_seg, n_win))}
+    if unit is not None:
+        out["unit_events"] = _events_view(unit, (bank.n_tmpl, n_seg, n_win))
+    return out
+
+
+def chisq_events(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, prefix: torch.Tensor, events,
+                 precision="fp32_ph64", p_bands: int = 16):
+    """chi^2 of Eq. (5) and rho at event records ({"raw": ...} of shape [n_seg, n_per_seg]); 0 where t < 0."""
+    prec = _prec(precision)
+    _require_cuda(stilde, Sn, prefix)
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    n_seg = int(stilde.shape[0])
+    raw = events["raw"]
+    n_per_seg = raw.numel() // 2 // n_seg
+    out = torch.empty((n_seg, n_per_seg), dtype=torch.float64, device=stilde.device)
+    rho = torch.empty_like(out)
+    g = grid.c()
+    L.check(_clib.mf_chisq_events(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn),
+                                  _ptr(prefix), prec, int(p_bands), _ptr(raw), n_per_seg, _ptr(out), _ptr(rho),
+                                  _stream(stilde.device)))
+    return out, rho
 
 
 def ifft(q: torch.Tensor, precision="fp32_ph64", workspace: torch.Tensor | None = None) -> torch.Tensor:

@@ -22,6 +22,10 @@ class MfPeak(C.Structure):
     _fields_ = [("rho", C.c_double), ("j", C.c_int32), ("n_above", C.c_int32)]
 
 
+class MfEvent(C.Structure):
+    _fields_ = [("rho", C.c_double), ("j", C.c_int32), ("t", C.c_int32)]
+
+
 class MfFilterOpts(C.Structure):
     _fields_ = [("rho_threshold", C.c_double), ("j_begin", C.c_int64), ("j_end", C.c_int64),
                 ("series_units_dev", C.c_void_p), ("n_series", C.c_int32)]
@@ -44,6 +48,9 @@ EXPORTS = [
     "mf_spa_bank", "mf_filter", "mf_ifft_workspace_bytes", "mf_ifft", "mf_snr_grad",
     "mf_timing_enable", "mf_timing_read", "mf_probe_copy", "mf_filter_plan", "mf_plan_candidates", "mf_set_plan",
     "mf_template_metric", "mf_chisq", "mf_filter_chisq", "mf_filter_chisq_workspace_bytes",
+    "mf_psd_prefix", "mf_rfft", "mf_rfft_workspace_bytes",
+    "mf_filter_events", "mf_filter_events_workspace_bytes", "mf_chisq_events", "mf_timing_read_split",
+    "mf_filter_chisq_plan",
 ]
 
 _lib = None
@@ -84,6 +91,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_timing_enable.argtypes = [i32]
     lib.mf_timing_read.restype = C.c_int
     lib.mf_timing_read.argtypes = [P(dbl), P(i64), P(i64), P(i64)]
+    lib.mf_filter_chisq_plan.restype = C.c_int
+    lib.mf_filter_chisq_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
+    lib.mf_timing_read_split.restype = C.c_int
+    lib.mf_timing_read_split.argtypes = [P(dbl), P(i64), P(i64), P(i64)]
     lib.mf_filter_plan.restype = C.c_int
     lib.mf_filter_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
     lib.mf_plan_candidates.restype = i32
@@ -97,6 +108,18 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_filter_chisq.restype = C.c_int
     lib.mf_filter_chisq.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, vp, C.c_int, i32, P(MfFilterOpts), vp, sz, vp,
                                     vp, vp, vp, vp]
+    lib.mf_psd_prefix.restype = C.c_int
+    lib.mf_psd_prefix.argtypes = [P(MfGrid), vp, vp, vp]
+    lib.mf_rfft_workspace_bytes.restype = sz
+    lib.mf_rfft_workspace_bytes.argtypes = [i64, C.c_int, i64]
+    lib.mf_rfft.restype = C.c_int
+    lib.mf_rfft.argtypes = [i64, dbl, C.c_int, vp, vp, i64, vp, sz, vp]
+    lib.mf_filter_events_workspace_bytes.restype = sz
+    lib.mf_filter_events_workspace_bytes.argtypes = [P(MfGrid), C.c_int, i64, i64, i32]
+    lib.mf_filter_events.restype = C.c_int
+    lib.mf_filter_events.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, C.c_int, dbl, i32, vp, sz, vp, vp, vp, vp]
+    lib.mf_chisq_events.restype = C.c_int
+    lib.mf_chisq_events.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, vp, C.c_int, i32, vp, i64, vp, vp, vp]
     lib.mf_template_metric.restype = C.c_int
     lib.mf_template_metric.argtypes = [P(MfGrid), vp, vp, i64, vp, vp, vp]
     lib.mf_probe_copy.restype = C.c_int

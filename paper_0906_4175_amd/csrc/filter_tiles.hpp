@@ -66,6 +66,17 @@ __device__ __forceinline__ void powers(cx<T> w, cx<T>* p) {
 
 __host__ __device__ constexpr int pad16(int k) { return k + (k >> 4); }
 
+// Event keys: larger key = larger |z|^2, then lower index.  FP32 keeps the
+// float bits and the sample index; FP64 keeps |z|^2 to 36 mantissa bits and
+// the index inside the window (windows of at most 2^16 samples).
+__device__ __forceinline__ unsigned long long event_key32(float zz, unsigned int j) {
+    return ((unsigned long long)__float_as_uint(zz) << 32) | (unsigned long long)(0xffffffffu - j);
+}
+__device__ __forceinline__ unsigned long long event_key64(double zz, unsigned int j_in_window) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(zz) & ~0xffffull;
+    return b | (unsigned long long)(0xffffu - j_in_window);
+}
+
 __device__ __forceinline__ bool better64(double zz, int j, double bzz, int bj) {
     const bool an = zz != zz, bn = bzz != bzz;
     if (an != bn) return an;
@@ -354,6 +365,20 @@ struct Pass2 {
                                 if (count_on) {
 #pragma unroll
                                     for (int r = 0; r < R; ++r) cnt += (zz[r] >= thr2) ? 1u : 0u;
+                                }
+                                if (a.ev_keys != nullptr) {
+                                    // events: rare samples at or above the threshold update their window
+                                    unsigned long long* ek = a.ev_keys + u * (N >> a.ev_log2w);
+#pragma unroll
+                                    for (int r = 0; r < R; ++r) {
+                                        if (zz[r] >= thr2) {
+                                            const unsigned int jg = (unsigned int)(j1 + N1 * (j + r * NSPAN));
+                                            const unsigned long long key =
+                                                F64 ? event_key64((double)zz[r], jg & ((1u << a.ev_log2w) - 1u))
+                                                    : event_key32((float)zz[r], jg);
+                                            atomicMax(ek + (jg >> a.ev_log2w), key);
+                                        }
+                                    }
                                 }
                                 if constexpr (F64) {
 #pragma unroll

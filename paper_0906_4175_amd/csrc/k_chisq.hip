@@ -32,20 +32,40 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     return tot;
 }
 
+// One work-group per output: a unit's peak (peaks != nullptr; output u =
+// t * n_seg + s) or an event record (events [n_seg][n_per_seg]; entries with
+// t < 0 give 0).
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_chisq(int64_t n, double df, const mf_bank_entry* bank, int64_t n_tmpl,
                                               int64_t n_seg, const cx<T>* stilde, const double* Sn, const double* P,
-                                              int p, const mf_peak* peaks, double* chisq, double* rho_out) {
+                                              int p, const mf_peak* peaks, const mf_event* events, int64_t n_per_seg,
+                                              double* chisq, double* rho_out) {
     __shared__ int64_t edge[kMaxBands + 1];
     __shared__ double zr[kMaxBands], zi[kMaxBands];
     __shared__ double scratch[NT / 64];
     const int tid = threadIdx.x;
-    const int64_t u = blockIdx.x;  // public unit id t * n_seg + s
-    const int64_t t = u / n_seg, s = u % n_seg;
-    const mf_bank_entry e = bank[t];
+    const int64_t u = blockIdx.x;
+    int64_t t, s, j;
+    if (events) {
+        const mf_event ev = events[u];
+        if (ev.t < 0) {
+            if (tid == 0) {
+                chisq[u] = 0.0;
+                if (rho_out) rho_out[u] = 0.0;
+            }
+            return;
+        }
+        t = ev.t;
+        s = u / n_per_seg;
+        j = ev.j;
+    } else {
+        t = u / n_seg;
+        s = u % n_seg;
+        j = peaks[u].j;
+    }
+    const mf_bank_entry e = bank[t < n_tmpl ? t : 0];
     const int64_t klo = e.k_lo, khi = e.k_hi;
-    const int64_t j = peaks[u].j;
-    if (j < 0 || j >= n || khi > n / 2 - 1 || klo < 1 || khi < klo) {
+    if (t >= n_tmpl || j < 0 || j >= n || khi > n / 2 - 1 || klo < 1 || khi < klo) {
         if (tid == 0) {
             chisq[u] = NAN;
             if (rho_out) rho_out[u] = NAN;
@@ -113,16 +133,17 @@ __global__ void __launch_bounds__(NT) k_chisq(int64_t n, double df, const mf_ban
 
 hipError_t launch_chisq(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
                         const void* stilde, int64_t n_seg, const double* Sn, const double* prefix, int p,
-                        const mf_peak* peaks, double* chisq, double* rho, hipStream_t s) {
+                        const mf_peak* peaks, const mf_event* events, int64_t n_per_seg, double* chisq, double* rho,
+                        hipStream_t s) {
     const double df = fs / (double)n;
     constexpr int NT = 256;
-    const unsigned blocks = (unsigned)(n_tmpl * n_seg);
+    const unsigned blocks = (unsigned)(events ? n_seg * n_per_seg : n_tmpl * n_seg);
     if (prec == MF_FP64)
         hipLaunchKernelGGL((k_chisq<double, NT>), dim3(blocks), dim3(NT), 0, s, n, df, bank, n_tmpl, n_seg,
-                           (const cx<double>*)stilde, Sn, prefix, p, peaks, chisq, rho);
+                           (const cx<double>*)stilde, Sn, prefix, p, peaks, events, n_per_seg, chisq, rho);
     else
         hipLaunchKernelGGL((k_chisq<float, NT>), dim3(blocks), dim3(NT), 0, s, n, df, bank, n_tmpl, n_seg,
-                           (const cx<float>*)stilde, Sn, prefix, p, peaks, chisq, rho);
+                           (const cx<float>*)stilde, Sn, prefix, p, peaks, events, n_per_seg, chisq, rho);
     return hipGetLastError();
 }
 

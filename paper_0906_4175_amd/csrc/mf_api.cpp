@@ -322,9 +322,16 @@ mf_status mf_spa_bank(const mf_grid* grid, const double* mc_host, const double* 
     return ok();
 }
 
-mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev, int64_t n_seg,
-                    const double* Sn_dev, mf_precision prec, const mf_filter_opts* opts, void* workspace_dev,
-                    size_t workspace_bytes, mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Body of mf_filter; ev_keys (nullable, zeroed by the caller) turns on the
+// per-window event keys of pass 2.
+mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
+                      int64_t n_seg, const double* Sn_dev, mf_precision prec, const mf_filter_opts* opts,
+                      void* workspace_dev, size_t workspace_bytes, mf_peak* peaks_dev, void* rho_dev,
+                      mf_stream_t stream, unsigned long long* ev_keys, int ev_log2w) {
     int l, klo;
     mf_status st = check_grid(grid, &l, &klo);
     if (st != MF_OK) return st;
@@ -372,6 +379,8 @@ mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, c
     a.series_units = o.series_units_dev;
     a.n_series = o.n_series;
     a.rho = rho_dev;
+    a.ev_keys = ev_keys;
+    a.ev_log2w = ev_log2w;
 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);
@@ -388,30 +397,13 @@ mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, c
             x.units = (a.n_units - x.unit0) < upb ? (a.n_units - x.unit0) : upb;
         }
     };
-    // sampled launches get an event pair on the stream (measurement hook)
-    auto timed_launch = [&](const mf::FilterArgs& a1, const mf::FilterArgs& a2, auto&& launch) -> mf_status {
-        const bool timed = g_timing.stride > 0 && (g_timing.batch_counter++ % g_timing.stride) == 0;
-        TimedLaunch t{};
-        if (timed) {
-            t = TimedLaunch{timing_event(), timing_event(), a1.units, a2.units};
-            if (!t.start || !t.stop) return fail(MF_E_HIP, "timing event creation failed");
-            hipEventRecord(t.start, s);
-        }
-        hipError_t le = launch();
-        if (le != hipSuccess) return hip_fail(le, "mf_filter launch");
-        if (timed) {
-            hipEventRecord(t.stop, s);
-            g_timing.pending.push_back(t);
-        }
-        return MF_OK;
-    };
     if (p.fused) {
         // step b: pass 1 of batch b into buffer b%2, pass 2 of batch b-1 from buffer (b-1)%2
         for (int64_t b = 0; b <= nb; ++b) {
             mf::FilterArgs a1 = a, a2 = a;
             batch(a1, b, (int)(b & 1));
             batch(a2, b - 1, (int)((b + 1) & 1));
-            st = timed_launch(a1, a2, [&] { return mf::launch_step(p, prec, a1, a2, s); });
+            st = timed_launch(s, a1.units, a2.units, [&] { return mf::launch_step(p, prec, a1, a2, s); });
             if (st != MF_OK) return st;
         }
     } else {
@@ -419,14 +411,85 @@ mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, c
             mf::FilterArgs a1 = a, none = a;
             batch(a1, b, 0);
             batch(none, -1, 0);
-            st = timed_launch(a1, none, [&] { return mf::launch_pass1(p, prec, false, a1, s); });
+            st = timed_launch(s, a1.units, none.units, [&] { return mf::launch_pass1(p, prec, false, a1, s); });
             if (st != MF_OK) return st;
-            st = timed_launch(none, a1, [&] { return mf::launch_pass2(p, prec, false, a1, s); });
+            st = timed_launch(s, none.units, a1.units, [&] { return mf::launch_pass2(p, prec, false, a1, s); });
             if (st != MF_OK) return st;
         }
     }
     e = mf::launch_finalize(p, prec, a, peaks_dev, s);
     if (e != hipSuccess) return hip_fail(e, "mf_filter finalize");
+    return ok();
+}
+
+size_t events_scratch_bytes(int64_t n, int64_t n_tmpl, int64_t n_seg, int log2w) {
+    const int64_t n_win = n >> log2w;
+    const size_t keys = (size_t)(n_tmpl * n_seg * n_win) * 8;
+    const size_t unit_ev = (size_t)(n_tmpl * n_seg * n_win) * sizeof(mf_event);
+    const size_t best = (size_t)(n_seg * n_win) * sizeof(mf_event);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return al(keys) + al(unit_ev) + al(best);
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev, int64_t n_seg,
+                    const double* Sn_dev, mf_precision prec, const mf_filter_opts* opts, void* workspace_dev,
+                    size_t workspace_bytes, mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream) {
+    return filter_impl(grid, bank_dev, n_tmpl, stilde_dev, n_seg, Sn_dev, prec, opts, workspace_dev, workspace_bytes,
+                       peaks_dev, rho_dev, stream, nullptr, 0);
+}
+
+size_t mf_filter_events_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl, int64_t n_seg,
+                                        int32_t log2_window) {
+    int l, klo;
+    if (check_grid(grid, &l, &klo) != MF_OK || !valid_prec(prec) || n_tmpl < 1 || n_seg < 1 || log2_window < 4 ||
+        log2_window > 16 || log2_window > l)
+        return 0;
+    const size_t base = mf_filter_workspace_bytes(grid, prec, n_tmpl, n_seg);
+    if (base == 0) return 0;
+    return ((base + 255) & ~(size_t)255) + events_scratch_bytes(grid->n, n_tmpl, n_seg, log2_window);
+}
+
+mf_status mf_filter_events(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
+                           int64_t n_seg, const double* Sn_dev, mf_precision prec, double rho_threshold,
+                           int32_t log2_window, void* workspace_dev, size_t workspace_bytes, mf_peak* peaks_dev,
+                           mf_event* unit_events_dev, mf_event* seg_events_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!seg_events_dev || !workspace_dev || !peaks_dev || !bank_dev)
+        return fail(MF_E_ARG, "null pointer argument");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (!(rho_threshold > 0.0) || !isfinite(rho_threshold))
+        return fail(MF_E_ARG, "rho_threshold must be positive and finite");
+    if (log2_window < 4 || log2_window > 16 || log2_window > l)
+        return fail(MF_E_ARG, "log2_window=%d outside [4, min(16, log2 N)]", (int)log2_window);
+    if (n_tmpl < 1 || n_seg < 1 || n_tmpl * n_seg > (int64_t(1) << 31) - 1)
+        return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld", (long long)n_tmpl, (long long)n_seg);
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(MF_E_ARG, "workspace must be 256-byte aligned");
+    const size_t need = mf_filter_events_workspace_bytes(grid, prec, n_tmpl, n_seg, log2_window);
+    if (workspace_bytes < need) return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, need);
+    const size_t base = (mf_filter_workspace_bytes(grid, prec, n_tmpl, n_seg) + 255) & ~(size_t)255;
+    const int64_t n_win = grid->n >> log2_window;
+    char* ev = (char*)workspace_dev + base;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    unsigned long long* keys = (unsigned long long*)ev;
+    mf_event* unit_ev = (mf_event*)(ev + al((size_t)(n_tmpl * n_seg * n_win) * 8));
+    mf_event* best = (mf_event*)((char*)unit_ev + al((size_t)(n_tmpl * n_seg * n_win) * sizeof(mf_event)));
+    if (unit_events_dev) unit_ev = unit_events_dev;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = mf::launch_fill_u64(keys, n_tmpl * n_seg * n_win, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter_events clear");
+    mf_filter_opts o{rho_threshold, 0, 0, nullptr, 0};
+    st = filter_impl(grid, bank_dev, n_tmpl, stilde_dev, n_seg, Sn_dev, prec, &o, workspace_dev, base, peaks_dev,
+                     nullptr, stream, keys, log2_window);
+    if (st != MF_OK) return st;
+    e = mf::launch_events(keys, n_tmpl, n_seg, n_win, log2_window, prec == MF_FP64, (const mf_bank_entry*)bank_dev,
+                          unit_ev, best, seg_events_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter_events clustering");
     return ok();
 }
 
@@ -473,6 +536,56 @@ mf_status mf_ifft(int64_t n, mf_precision prec, const void* q_dev, void* z_dev, 
     return ok();
 }
 
+size_t mf_rfft_workspace_bytes(int64_t n, mf_precision prec, int64_t batch) {
+    const int l = log2_exact(n);
+    if (l < mf::kMinLog2N + 1 || l > mf::kMaxLog2N + 1 || !valid_prec(prec) || batch < 1) {
+        fail(MF_E_ARG, "bad n/precision/batch");
+        return 0;
+    }
+    const size_t half = (size_t)batch * (size_t)(n / 2) * mf::cx_bytes(prec);
+    const size_t inter = mf_ifft_workspace_bytes(n / 2, prec, batch);
+    return 2 * ((half + 255) & ~(size_t)255) + inter;
+}
+
+mf_status mf_rfft(int64_t n, double fs, mf_precision prec, const void* x_dev, void* stilde_dev, int64_t batch,
+                  void* workspace_dev, size_t workspace_bytes, mf_stream_t stream) {
+    const int l = log2_exact(n);
+    if (l < mf::kMinLog2N + 1 || l > mf::kMaxLog2N + 1)
+        return fail(MF_E_SHAPE, "n=%lld must be a power of two in [2^%d, 2^%d]", (long long)n, mf::kMinLog2N + 1,
+                    mf::kMaxLog2N + 1);
+    if (!(fs > 0.0) || !isfinite(fs)) return fail(MF_E_ARG, "fs must be positive and finite");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (!x_dev || !stilde_dev || !workspace_dev) return fail(MF_E_ARG, "null pointer argument");
+    if (batch < 1) return fail(MF_E_ARG, "batch=%lld", (long long)batch);
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(MF_E_ARG, "workspace must be 256-byte aligned");
+    const size_t need = mf_rfft_workspace_bytes(n, prec, batch);
+    if (workspace_bytes < need) return fail(MF_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, need);
+    const int64_t m = n / 2;
+    const size_t half = (((size_t)batch * (size_t)m * mf::cx_bytes(prec)) + 255) & ~(size_t)255;
+    char* ws = (char*)workspace_dev;
+    void* y = ws;
+    void* z = ws + half;
+    void* inter = ws + 2 * half;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = mf::launch_rfft_pack(prec, x_dev, y, m, batch, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_rfft pack");
+    mf_status st = mf_ifft(m, prec, y, z, batch, inter, workspace_bytes - 2 * half, stream);
+    if (st != MF_OK) return st;
+    e = mf::launch_rfft_post(prec, z, stilde_dev, m, batch, 1.0 / fs, s);
+    if (e != hipSuccess) return hip_fail(e, "mf_rfft post");
+    return ok();
+}
+
+mf_status mf_psd_prefix(const mf_grid* grid, const double* Sn_dev, double* prefix_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!Sn_dev || !prefix_dev) return fail(MF_E_ARG, "null pointer argument");
+    hipError_t e = mf::launch_prefix(grid->n, grid->fs, Sn_dev, prefix_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mf_psd_prefix");
+    return ok();
+}
+
 mf_status mf_snr_grad(const mf_grid* grid, const double* theta_dev, const int32_t* khi_dev, const int32_t* seg_dev,
                       int64_t n, const void* stilde_dev, int64_t n_seg, const double* Sn_dev, mf_precision prec,
                       double* Z_dev, double* rho2_dev, const double* gbar_dev, double* grad_dev, mf_stream_t stream) {
@@ -500,6 +613,18 @@ size_t mf_filter_chisq_workspace_bytes(const mf_grid* grid, mf_precision prec, i
     const mf::Plan p = mf::band_plan(l, prec);
     if (p.log2n != l) return 0;
     return mf::band_layout(p, prec, grid->n, n_tmpl, n_seg, p_bands).total;
+}
+
+mf_status mf_filter_chisq_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!valid_prec(prec) || !plan) return fail(MF_E_ARG, "bad precision or null plan");
+    const mf::Plan p = mf::band_plan(l, prec);
+    if (p.log2n != l) return fail(MF_E_UNSUPPORTED, "no band-mode plan for n=%lld", (long long)grid->n);
+    const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, 0};
+    for (int i = 0; i < 8; ++i) plan[i] = v[i];
+    return ok();
 }
 
 mf_status mf_filter_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
@@ -589,8 +714,30 @@ mf_status mf_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, co
     if (n_tmpl < 1 || n_seg < 1 || n_tmpl * n_seg > (int64_t(1) << 31) - 1)
         return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld", (long long)n_tmpl, (long long)n_seg);
     hipError_t e = mf::launch_chisq(grid->n, grid->fs, prec, (const mf_bank_entry*)bank_dev, n_tmpl, stilde_dev, n_seg,
-                                    Sn_dev, prefix_dev, p_bands, peaks_dev, chisq_dev, rho_dev, (hipStream_t)stream);
+                                    Sn_dev, prefix_dev, p_bands, peaks_dev, nullptr, 0, chisq_dev, rho_dev,
+                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "mf_chisq");
+    return ok();
+}
+
+mf_status mf_chisq_events(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
+                          int64_t n_seg, const double* Sn_dev, const double* prefix_dev, mf_precision prec,
+                          int32_t p_bands, const mf_event* events_dev, int64_t n_per_seg, double* chisq_dev,
+                          double* rho_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!bank_dev || !stilde_dev || !Sn_dev || !prefix_dev || !events_dev || !chisq_dev)
+        return fail(MF_E_ARG, "null pointer argument");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (p_bands < 2 || p_bands > 64) return fail(MF_E_ARG, "p_bands=%d outside [2, 64]", (int)p_bands);
+    if (n_tmpl < 1 || n_seg < 1 || n_per_seg < 1 || n_seg * n_per_seg > (int64_t(1) << 31) - 1)
+        return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld n_per_seg=%lld", (long long)n_tmpl, (long long)n_seg,
+                    (long long)n_per_seg);
+    hipError_t e = mf::launch_chisq(grid->n, grid->fs, prec, (const mf_bank_entry*)bank_dev, n_tmpl, stilde_dev, n_seg,
+                                    Sn_dev, prefix_dev, p_bands, nullptr, events_dev, n_per_seg, chisq_dev, rho_dev,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mf_chisq_events");
     return ok();
 }
 
@@ -623,29 +770,40 @@ mf_status mf_timing_enable(int32_t stride) {
     return ok();
 }
 
-mf_status mf_timing_read(double* ms, int64_t* launches, int64_t* pass1_units, int64_t* pass2_units) {
+mf_status mf_timing_read_split(double ms[3], int64_t launches[3], int64_t pass1_units[3], int64_t pass2_units[3]) {
     if (!ms || !launches || !pass1_units || !pass2_units) return fail(MF_E_ARG, "null pointer argument");
-    double tot = 0.0;
-    int64_t cnt = 0, u1 = 0, u2 = 0;
+    for (int c = 0; c < 3; ++c) {
+        ms[c] = 0.0;
+        launches[c] = pass1_units[c] = pass2_units[c] = 0;
+    }
     mf_status st = MF_OK;
     for (const TimedLaunch& t : g_timing.pending) {
         hipError_t e = hipEventSynchronize(t.stop);
         float el = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&el, t.start, t.stop);
         if (e != hipSuccess && st == MF_OK) st = hip_fail(e, "mf_timing_read");
-        tot += el;
-        cnt += 1;
-        u1 += t.units1;
-        u2 += t.units2;
+        const int c = t.units2 == 0 ? 0 : (t.units1 == 0 ? 1 : 2);
+        ms[c] += el;
+        launches[c] += 1;
+        pass1_units[c] += t.units1;
+        pass2_units[c] += t.units2;
         g_timing.pool.push_back(t.start);
         g_timing.pool.push_back(t.stop);
     }
     g_timing.pending.clear();
-    *ms = tot;
-    *launches = cnt;
-    *pass1_units = u1;
-    *pass2_units = u2;
     return st == MF_OK ? ok() : st;
+}
+
+mf_status mf_timing_read(double* ms, int64_t* launches, int64_t* pass1_units, int64_t* pass2_units) {
+    if (!ms || !launches || !pass1_units || !pass2_units) return fail(MF_E_ARG, "null pointer argument");
+    double m[3];
+    int64_t n[3], u1[3], u2[3];
+    mf_status st = mf_timing_read_split(m, n, u1, u2);
+    *ms = m[0] + m[1] + m[2];
+    *launches = n[0] + n[1] + n[2];
+    *pass1_units = u1[0] + u1[1] + u1[2];
+    *pass2_units = u2[0] + u2[1] + u2[2];
+    return st;
 }
 
 }  // extern "C"

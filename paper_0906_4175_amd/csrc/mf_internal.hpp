@@ -65,6 +65,10 @@ struct FilterArgs {
     int32_t p_bands;
     void* qbuf;               // [units][n/2] template x weight product, [k1][k2]
     void* chi_series;         // chi^2 series output [n_series][n]
+    // events: per (unit, window of 2^ev_log2w samples) u64 keys of the loudest
+    // sample at or above the threshold (see event_key32 / event_key64)
+    unsigned long long* ev_keys;  // [n_units][n >> ev_log2w], unit u = s * n_tmpl + t
+    int32_t ev_log2w;
 };
 
 // Workspace carve-up of mf_filter_chisq (band mode).
@@ -89,6 +93,15 @@ hipError_t launch_pass1_band(const Plan& p, mf_precision prec, const FilterArgs&
 hipError_t launch_pass2_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s);
 hipError_t launch_finalize_band(const Plan& p, const FilterArgs& a, mf_peak* peaks, double* chisq, hipStream_t s);
 
+hipError_t launch_rfft_pack(mf_precision prec, const void* x, void* y, int64_t m, int64_t batch, hipStream_t s);
+hipError_t launch_rfft_post(mf_precision prec, const void* z, void* out, int64_t m, int64_t batch, double dt,
+                            hipStream_t s);
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t s);
+hipError_t launch_events(const unsigned long long* keys, int64_t n_tmpl, int64_t n_seg, int64_t n_win, int log2w,
+                         bool f64, const mf_bank_entry* bank, mf_event* unit_ev, mf_event* best, mf_event* seg_ev,
+                         hipStream_t s);
+
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_psd(int64_t n, double fs, double f_low, double f0, int k_lo, double* Sn, hipStream_t s);
 hipError_t launch_prefix(int64_t n, double fs, const double* Sn, double* prefix, hipStream_t s);
@@ -100,7 +113,8 @@ hipError_t launch_spa_synth(int64_t n, double fs, mf_precision prec, const mf_ba
                             void* htilde, hipStream_t s);
 hipError_t launch_chisq(int64_t n, double fs, mf_precision prec, const mf_bank_entry* bank, int64_t n_tmpl,
                         const void* stilde, int64_t n_seg, const double* Sn, const double* prefix, int p,
-                        const mf_peak* peaks, double* chisq, double* rho, hipStream_t s);
+                        const mf_peak* peaks, const mf_event* events, int64_t n_per_seg, double* chisq, double* rho,
+                        hipStream_t s);
 hipError_t launch_metric(int64_t n, double fs, int k_lo, const double* theta, const int32_t* khi, int64_t count,
                          const double* Sn, double* metric, hipStream_t s);
 hipError_t launch_snr_grad(int64_t n, double fs, int k_lo, mf_precision prec, const double* theta,

@@ -5,7 +5,7 @@ Runs, in one process: the calibration copy kernel over a buffer of known size
 workload for a few steps.  Usage (from the repository root):
 
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o run -- \\
-      python3 paper_0906_4175_amd/profile_run.py --workload 2 --steps 2
+      python3 paper_0906_4175_amd/profile_run.py --workload 2 --steps 2 [--chisq-bands 16]
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--precision", default="fp32_ph64")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--chisq-bands", type=int, default=0, help="also run the chi^2 band mode with p bands")
     args = ap.parse_args()
 
     import torch
@@ -64,6 +65,14 @@ def main():
     for _ in range(args.steps):
         res = mf.filter(grid, bank, st, Sn, args.precision, workspace=ws)
     torch.cuda.synchronize()
+    if args.chisq_bands > 0:
+        del ws
+        _, P = mf.psd(grid, prefix=True, device=dev)
+        wsb = torch.empty(mf.filter_chisq_workspace_bytes(grid, args.precision, bank.n_tmpl, wl.n_seg,
+                                                          args.chisq_bands), dtype=torch.uint8, device=dev)
+        for _ in range(args.steps):
+            mf.filter_chisq(grid, bank, st, Sn, P, args.precision, p_bands=args.chisq_bands, workspace=wsb)
+        torch.cuda.synchronize()
     print(f"profile_run done: copy {args.copy_mib} MiB, {args.steps} steps of {wl.name}, "
           f"max rho {float(res['rho'].max()):.4f}")
 

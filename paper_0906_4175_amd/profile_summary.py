@@ -18,7 +18,8 @@ import os
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f) for f in ("k_filter.hip", "mf_device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f)
+                  for f in ("k_filter.hip", "k_filter_chisq.hip", "filter_tiles.hpp", "mf_device.hpp")]
 
 
 def kernel_hash() -> str:
@@ -30,8 +31,10 @@ def kernel_hash() -> str:
 
 
 def short(name: str) -> str:
-    for key in ("k_pass1", "k_pass2", "k_step", "k_copy_probe", "k_finalize32", "k_finalize64", "k_weights",
-                "k_sigma", "k_psd", "k_spa_synth", "k_snr_grad", "k_prefix"):
+    for key in ("k_pass1_band", "k_pass2_band", "k_pass1", "k_pass2", "k_step", "k_copy_probe", "k_finalize32",
+                "k_finalize64", "k_finalize_band", "k_band_table", "k_weights", "k_sigma", "k_psd", "k_spa_synth",
+                "k_snr_grad", "k_prefix", "k_chisq", "k_events_unit", "k_events_best", "k_events_merge",
+                "k_fill_u64", "k_rfft_pack", "k_rfft_post"):
         if key in name:
             prec = "fp64" if "<double" in name else ("fp32" if "<float" in name else "")
             return f"{key}_{prec}" if prec else key

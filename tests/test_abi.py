@@ -178,3 +178,33 @@ def test_tune_cache_corrupt_and_foreign(tmp_path):
     assert tune.current_plan(1 << 20, 1)["units_per_batch"] == 32
     tune.set_plan(1 << 20, 1, None)
     assert tune.current_plan(1 << 20, 1)["n1"] == 256
+
+
+def test_chisq_entry_points_validation(lib):
+    g = _grid()
+    vp = C.c_void_p
+    # point chi^2: bad band count, null pointers, bad precision
+    args = lambda p=16, prec=1, peaks=vp(256): (C.byref(g), vp(256), 4, vp(256), 1, vp(256), vp(256), prec, p, peaks,
+                                                vp(256), None, None)
+    assert lib.mf_chisq(*args(p=1)) == -1
+    assert b"p_bands" in lib.mf_last_error()
+    assert lib.mf_chisq(*args(p=65)) == -1
+    assert lib.mf_chisq(*args(peaks=None)) == -1
+    assert lib.mf_chisq(*args(prec=9)) == -1
+    # band-mode filter: workspace size depends on p and the batch, rejects bad p
+    w16 = int(lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 8, 2, 16))
+    w64 = int(lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 8, 2, 64))
+    assert w64 > w16 > 0
+    # weights + product + one intermediate per unit of the batch
+    assert w16 >= 2 * ((1 << 19) + 1) * 8 + 16 * (3 << 19) * 8
+    assert lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 8, 2, 1) == 0
+    assert lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 8, 2, 65) == 0
+    fargs = lambda ws, p=16, chi=vp(256), opts=None, wsp=256: (
+        C.byref(g), vp(256), 8, vp(256), 2, vp(256), vp(256), 1, p, opts, vp(wsp), ws, vp(256), chi, None, None, None)
+    assert lib.mf_filter_chisq(*fargs(w16 - 1)) == -5
+    assert lib.mf_filter_chisq(*fargs(w16, chi=None)) == -1
+    assert lib.mf_filter_chisq(*fargs(w16, p=0)) == -1
+    assert lib.mf_filter_chisq(*fargs(w16, wsp=264)) == -1
+    su = L.MfFilterOpts(math.inf, 0, 0, vp(256), 2)  # series without output arrays
+    assert lib.mf_filter_chisq(*fargs(w16, opts=C.byref(su))) == -1
+    assert b"chisq_series" in lib.mf_last_error()

@@ -647,3 +647,257 @@ def test_filter_chisq_agrees_with_filter_and_point_chisq_full_size(mf):
     for t, s_i in [(0, 0), (len(mc) - 1, 1)]:
         c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], segs[s_i], Sn_ref, int(res["j"][t, s_i]), p)
         assert abs(float(res["chisq"][t, s_i]) - c_ref) <= 1e-9 * (c_ref + r_ref ** 2 + 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Time-domain input: forward real transform, caller-supplied PSD, N = 4 x 2^20
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("log2n", [11, 12, 15, 20, 22, 23])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ph64"])
+def test_rfft_matches_oracle(mf, log2n, prec):
+    print(f"[rfft] log2n={log2n} prec={prec}", flush=True)
+    n, fs = 1 << log2n, 4096.0
+    rng = np.random.Generator(np.random.PCG64(1000 + log2n))
+    batch = 3 if log2n <= 20 else 1
+    x = rng.standard_normal((batch, n))
+    if prec != "fp64":
+        x = x.astype(np.float32)
+    xs = torch.from_numpy(x).to(_dev())
+    got = mf.rfft(xs, fs, prec).cpu().numpy()
+    assert got.shape == (batch, n // 2 + 1)
+    for b in range(batch):
+        ref = O.segment_spectrum(x[b].astype(np.float64), fs)
+        err = np.max(np.abs(got[b] - ref)) / np.max(np.abs(ref))
+        assert err < (1e-13 if prec == "fp64" else 3e-6), (b, err)
+
+
+def _time_domain_segment(n, fs, seed, inj):
+    """Real strain: coloured noise and one injection, built in the frequency domain
+    (seeded generators, oracle template) and taken to the time domain."""
+    s, Sn_ref = D.segment(n, fs, seed, [inj], dtype=np.complex128)
+    x = np.fft.irfft(s * fs, n)  # s_k = dt sum_j x_j e^{-2 pi i jk/N}
+    return x, Sn_ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ph64"])
+def test_time_domain_input_end_to_end(mf, prec):
+    """Real 2^16-sample segments -> mf_rfft -> mf_filter, against the oracle on the same samples."""
+    print(f"[time-domain] prec={prec}", flush=True)
+    n, fs = 1 << 16, 2048.0
+    inj = dict(m1=1.4, m2=1.4, snr=11.0, j0=40001, phi0=1.3)
+    x, Sn_ref = _time_domain_segment(n, fs, synth.seed_sequence(15).spawn(1)[0], inj)
+    if prec != "fp64":
+        x = x.astype(np.float32)
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    mc, eta = synth.bank_small_grid()
+    bank = mf.spa_bank(g, mc, eta, Sn, prec)
+    st = mf.rfft(torch.from_numpy(x[None]).to(_dev()), fs, prec)
+    res = mf.filter(g, bank, st, Sn, prec, series_units=list(range(len(mc))))
+    s_ref = O.segment_spectrum(x.astype(np.float64), fs)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for t in range(len(mc)):
+        o = _oracle_unit(n, fs, mc[t], eta[t], s_ref, Sn_ref)
+        assert D.series_error(res["series"][t].cpu().numpy().astype(np.float64), o["series"]) < tol
+        assert D.peak_index_ok(int(res["j"][t, 0]), o["series"], o["j"], rel=1e-9 if prec == "fp64" else 2e-4)
+
+
+def test_caller_supplied_psd(mf):
+    """A PSD other than Eq. (2) (a rippled and lifted copy) through prefix, bank, filter and chi^2."""
+    print("[user psd]", flush=True)
+    n, fs, p = 1 << 16, 2048.0, 8
+    f = O.freqs(n, fs)
+    user = np.ones(n // 2 + 1)
+    user[1:] = O.psd_initial_ligo(f[1:]) * (1.0 + 0.3 * np.sin(f[1:] / 37.0)) + 0.05
+    Sn_ref = O.psd_from_array(user, n, fs, 40.0)
+    rng = np.random.Generator(np.random.PCG64(16))
+    k_lo = O.band_lo(n, fs, 40.0)
+    s = synth.coloured_noise(Sn_ref[k_lo: n // 2], fs / n, k_lo, n // 2 + 1, rng, dtype=np.complex128)
+    g = mf.Grid(n, fs)
+    Sn = torch.from_numpy(user).to(_dev())
+    P = mf.psd_prefix(g, Sn).cpu().numpy()
+    P_ref = O.prefix_sums(user, n, fs)
+    assert np.max(np.abs(P - P_ref) / np.maximum(P_ref[-1], 1e-300)) < 1e-13
+    mc, eta = synth.bank_small_grid()
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp64")
+    st = torch.from_numpy(s[None]).to(_dev())
+    res = mf.filter(g, bank, st, Sn, "fp64", series_units=list(range(len(mc))))
+    chi = mf.filter_chisq(g, bank, st, Sn, torch.from_numpy(P).to(_dev()), "fp64", p_bands=p)
+    for t in range(len(mc)):
+        o = _oracle_unit(n, fs, mc[t], eta[t], s, Sn_ref)
+        assert bank.sigma[t] == pytest.approx(o["sigma"], rel=1e-12)
+        assert D.series_error(res["series"][t].cpu().numpy(), o["series"]) < 1e-10
+        c_ref, _ = _chisq_ref(n, fs, mc[t], eta[t], s, Sn_ref, int(chi["j"][t, 0]), p)
+        assert float(chi["chisq"][t, 0]) == pytest.approx(c_ref, rel=1e-8, abs=1e-8)
+
+
+def test_filter_four_million_point_segments(mf):
+    """N = 4 x 2^20 (1024 s at 4096 Hz), 12 templates, one SNR-12 injection: sampled units vs the oracle."""
+    print("[filter 4M]", flush=True)
+    n, fs = 1 << 22, 4096.0
+    inj = dict(m1=1.4, m2=1.4, snr=12.0, j0=3000017, phi0=0.9)
+    s, Sn_ref = D.segment(n, fs, synth.seed_sequence(17).spawn(1)[0], [inj], dtype=np.complex64)
+    rng = synth.rngs(17, 1)[0]
+    mc, eta, _, _ = synth.bank_uneven(11, rng)
+    mc = np.append(mc, float(synth.mc_eta(1.4, 1.4)[0]))
+    eta = np.append(eta, 0.25)
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
+    st = torch.from_numpy(s[None]).to(_dev())
+    res = mf.filter(g, bank, st, Sn, "fp32_ph64", series_units=[0, 11])
+    for t, slot in [(0, 0), (11, 1)]:
+        o = _oracle_unit(n, fs, mc[t], eta[t], s, Sn_ref)
+        assert D.series_error(res["series"][slot].cpu().numpy().astype(np.float64), o["series"]) < 1e-4
+        assert float(res["rho"][t, 0]) == pytest.approx(o["rho"], rel=1e-4)
+        assert D.peak_index_ok(int(res["j"][t, 0]), o["series"], o["j"])
+    assert abs(int(res["j"][11, 0]) - inj["j0"]) <= 2  # the matched template finds the injection
+
+
+# ---------------------------------------------------------------------------
+# Events: threshold, time and template clustering; chi^2 at events
+# ---------------------------------------------------------------------------
+def _events_dict(evs, t_default=None):
+    """{window: (t, j, rho)} from oracle event lists."""
+    out = {}
+    for e in evs:
+        if len(e) == 3:
+            w, j, v = e
+            out[w] = (t_default, j, v)
+        else:
+            w, t, j, v = e
+            out[w] = (t, j, v)
+    return out
+
+
+def _gpu_events(view, *idx):
+    rho = view["rho"][idx].cpu().numpy()
+    j = view["j"][idx].cpu().numpy()
+    t = view["t"][idx].cpu().numpy()
+    return {w: (int(t[w]), int(j[w]), float(rho[w])) for w in range(len(t)) if t[w] >= 0}
+
+
+def _borderline(series, w, W, th, rel):
+    """Window w's decision is within rel of a tie: its winner near the threshold, or an
+    adjacent winner within W samples near its value."""
+    js, vals = O.window_maxima(series, W)
+    v = vals[w]
+    if abs(v - th) <= rel * th:
+        return True
+    for w2 in (w - 1, w + 1):
+        if 0 <= w2 < len(js) and abs(js[w2] - js[w]) <= W and abs(vals[w2] - v) <= rel * v:
+            return True
+    # the winner inside the window itself is a near tie
+    seg = np.sort(series[w * W: (w + 1) * W])
+    return seg.size > 1 and seg[-1] - seg[-2] <= rel * seg[-1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ph64"])
+def test_events_match_oracle(mf, prec):
+    """N=2^16, 16 templates x 2 segments, threshold 4.0 (dense noise events), windows of 2^9."""
+    print(f"[events] prec={prec}", flush=True)
+    n, fs, th, lw = 1 << 16, 2048.0, 4.0, 9
+    W = 1 << lw
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    # injections at grid points of the bank, so that one template matches each
+    injs = [dict(m1=5.0 / 3.0, m2=5.0 / 3.0, snr=12.0, j0=20000, phi0=0.2),
+            dict(m1=7.0 / 3.0, m2=1.0, snr=9.0, j0=1023, phi0=2.2)]
+    segs = []
+    for i, inj in enumerate(injs):
+        s, Sn_ref = D.segment(n, fs, synth.seed_sequence(18).spawn(2)[i], [inj], dtype=cdt)
+        segs.append(s)
+    mc, eta = synth.bank_small_grid()
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    bank = mf.spa_bank(g, mc, eta, Sn, prec)
+    st = torch.from_numpy(np.stack(segs)).to(_dev())
+    res = mf.filter_events(g, bank, st, Sn, prec, threshold=th, log2_window=lw, unit_events=True)
+    rel = 1e-9 if prec == "fp64" else 2e-4
+    n_events = 0
+    for s_i in range(2):
+        per_t, series_t = {}, {}
+        for t in range(len(mc)):
+            o = _oracle_unit(n, fs, mc[t], eta[t], segs[s_i], Sn_ref)
+            series_t[t] = o["series"]
+            per_t[t] = O.unit_events(o["series"], th, W)
+            ref = _events_dict(per_t[t], t)
+            got = _gpu_events(res["unit_events"], t, s_i)
+            n_events += len(ref)
+            for w in set(ref) | set(got):
+                if w in ref and w in got:
+                    assert got[w][2] == pytest.approx(ref[w][2], rel=1e-10 if prec == "fp64" else 1e-4)
+                    assert D.peak_index_ok(got[w][1], o["series"], ref[w][1], rel=rel)
+                else:
+                    assert prec != "fp64" and _borderline(o["series"], w, W, th, rel), (t, s_i, w, ref.get(w),
+                                                                                          got.get(w))
+        ref_seg = _events_dict(O.segment_events(per_t, n, th, W))
+        got_seg = _gpu_events(res["seg_events"], s_i)
+        for w in set(ref_seg) | set(got_seg):
+            if w in ref_seg and w in got_seg and got_seg[w][0] == ref_seg[w][0]:
+                assert got_seg[w][2] == pytest.approx(ref_seg[w][2], rel=1e-10 if prec == "fp64" else 1e-4)
+            else:
+                # a different template or a missing window: only on a near tie across templates or windows
+                assert prec != "fp64", (s_i, w, ref_seg.get(w), got_seg.get(w))
+                vals = sorted((ev[2] for t in per_t for ev in per_t[t] if ev[0] in (w - 1, w, w + 1)), reverse=True)
+                assert len(vals) > 1 and vals[0] - vals[1] <= rel * vals[0] or any(
+                    _borderline(series_t[t], w, W, th, rel) for t in series_t), (s_i, w)
+        # each injection is a segment event of its matching template at (about) its sample
+        near = [ev for ev in got_seg.values() if abs(ev[1] - injs[s_i]["j0"]) <= 4]
+        assert near and near[0][2] > 0.7 * injs[s_i]["snr"]
+    assert n_events > 100  # dense enough to exercise the clustering
+
+
+def test_chisq_at_events_matches_oracle(mf):
+    print("[chisq events]", flush=True)
+    n, fs, th, lw, p = 1 << 16, 2048.0, 4.5, 10, 16
+    inj = dict(m1=1.4, m2=1.4, snr=12.0, j0=33000, phi0=0.8)
+    s, Sn_ref = D.segment(n, fs, synth.seed_sequence(19).spawn(1)[0], [inj], dtype=np.complex128)
+    mc, eta = synth.bank_small_grid()
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp64")
+    st = torch.from_numpy(s[None]).to(_dev())
+    res = mf.filter_events(g, bank, st, Sn, "fp64", threshold=th, log2_window=lw)
+    chi, rho = mf.chisq_events(g, bank, st, Sn, P, res["seg_events"], "fp64", p_bands=p)
+    ev = _gpu_events(res["seg_events"], 0)
+    assert len(ev) > 10
+    for w, (t, j, r) in ev.items():
+        c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], s, Sn_ref, j, p)
+        assert float(chi[0, w]) == pytest.approx(c_ref, rel=1e-9, abs=1e-9)
+        assert float(rho[0, w]) == pytest.approx(r, rel=1e-10)
+    empty = [w for w in range(n >> lw) if w not in ev]
+    assert all(float(chi[0, w]) == 0.0 for w in empty)
+
+
+def test_events_accuracy_statistic_fp32_vs_fp64(mf):
+    """The paper's accuracy figure on synthetic data: of the events found by both the FP32
+    (FP64-phase) and the FP64 path, more than 99% have rho within 0.03% and chi^2 within 0.5%."""
+    print("[events accuracy]", flush=True)
+    n, fs, th, lw, p, n_seg = 1 << 20, 4096.0, 4.0, 11, 16, 4
+    rng = synth.rngs(20, 1)[0]
+    mc, eta, _, _ = synth.bank_uneven(64, rng)
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    Sh = Sn.cpu().numpy()
+    k_lo = g.k_lo
+    rs = synth.rngs(20, n_seg + 1)[1:]
+    s = np.stack([synth.coloured_noise(Sh[k_lo: n // 2], g.df, k_lo, n // 2 + 1, r, dtype=np.complex64) for r in rs])
+    out = {}
+    for prec in ("fp32_ph64", "fp64"):
+        bank = mf.spa_bank(g, mc, eta, Sn, prec)
+        st = torch.from_numpy(s.astype(np.complex128 if prec == "fp64" else np.complex64)).to(_dev())
+        res = mf.filter_events(g, bank, st, Sn, prec, threshold=th, log2_window=lw)
+        chi, _ = mf.chisq_events(g, bank, st, Sn, P, res["seg_events"], prec, p_bands=p)
+        chi = chi.cpu().numpy()
+        ev = {}
+        for si in range(n_seg):
+            for w, e in _gpu_events(res["seg_events"], si).items():
+                ev[(si, w)] = (e[0], e[1], e[2], float(chi[si, w]))
+        out[prec] = ev
+    e32, e64 = out["fp32_ph64"], out["fp64"]
+    both = [k for k in e32 if k in e64 and e32[k][:2] == e64[k][:2]]
+    assert len(both) >= 0.99 * max(len(e32), len(e64)) and len(both) > 500
+    drho = np.array([abs(e32[k][2] / e64[k][2] - 1.0) for k in both])
+    dchi = np.array([abs(e32[k][3] / e64[k][3] - 1.0) for k in both])
+    assert np.mean(drho < 3e-4) > 0.99
+    assert np.mean(dchi < 5e-3) > 0.99

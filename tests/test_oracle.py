@@ -507,3 +507,114 @@ def test_chisq_flags_a_mismatched_glitch():
     assert chi2[int(np.argmax(np.abs(zl.sum(axis=0))))] > 5 * (2 * p - 2)
     chi2, zl = O.chisq_series(matched, Sn, h, n, fs, k_lo, k_hi, p)
     assert chi2[int(np.argmax(np.abs(zl.sum(axis=0))))] < 2 * (2 * p - 2)
+
+
+# ---------------------------------------------------------------------------
+# Time-domain input (R8) and caller-supplied PSD
+# ---------------------------------------------------------------------------
+def test_segment_spectrum_matches_explicit_double_loop():
+    rng = np.random.default_rng(7)
+    n, fs = 48, 16.0
+    x = rng.standard_normal(n)
+    want = np.zeros(n // 2 + 1, dtype=np.complex128)
+    for k in range(n // 2 + 1):
+        acc = 0.0 + 0.0j
+        for j in range(n):
+            acc += x[j] * complex(math.cos(2 * math.pi * j * k / n), -math.sin(2 * math.pi * j * k / n))
+        want[k] = acc / fs
+    got = O.segment_spectrum(x, fs)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_segment_spectrum_of_a_tone_and_parseval():
+    n, fs, k0 = 1 << 12, 512.0, 301
+    j = np.arange(n)
+    x = 2.5 * np.cos(2 * np.pi * k0 * j / n + 0.4)
+    s = O.segment_spectrum(x, fs)
+    # a real tone at bin k0 puts A N/2 e^{i phi} dt into bin k0 and nothing elsewhere
+    assert abs(s[k0] - 2.5 * n / 2 * np.exp(0.4j) / fs) < 1e-9
+    others = np.delete(s, k0)
+    assert np.max(np.abs(others)) < 1e-9
+    rng = np.random.default_rng(8)
+    y = rng.standard_normal(n)
+    X = O.segment_spectrum(y, fs) * fs
+    energy = (abs(X[0]) ** 2 + abs(X[-1]) ** 2 + 2 * np.sum(np.abs(X[1:-1]) ** 2)) / n
+    assert energy == pytest.approx(np.sum(y ** 2), rel=1e-12)
+
+
+def test_prefix_sums_give_sigma_and_ignore_out_of_band_values():
+    n, fs, f_low = 1 << 14, 1024.0, 40.0
+    Sn = O.psd_bins(n, fs, f_low)
+    P = O.prefix_sums(Sn, n, fs)
+    mc, eta = map(float, synth.mc_eta(1.4, 1.4))
+    k_lo, k_hi = O.band(n, fs, f_low, mc, eta)
+    h = O.spa_template(n, fs, f_low, mc, eta)
+    assert 4 * (fs / n) * (P[k_hi] - P[k_lo - 1]) == pytest.approx(O.sigma_sq(h, Sn, fs / n), rel=1e-12)
+    assert np.all(P[:k_lo] == 0.0) and np.all(np.diff(P) >= 0.0)
+    # a full-range user PSD restricted to the band equals the band-limited one
+    f = O.freqs(n, fs)
+    user = np.empty(n // 2 + 1)
+    user[1:] = O.psd_initial_ligo(f[1:])
+    user[0] = 1.0
+    R = O.psd_from_array(user, n, fs, f_low)
+    assert np.array_equal(np.isinf(R), np.isinf(Sn))
+    fin = np.isfinite(Sn)
+    assert np.max(np.abs(R[fin] / Sn[fin] - 1.0)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Events (R17): hand-built series with their event lists worked out by hand
+# ---------------------------------------------------------------------------
+def test_unit_events_isolated_peak_and_threshold():
+    rho = np.zeros(64)
+    rho[10] = 6.0
+    rho[40] = 4.0
+    assert O.unit_events(rho, 5.0, 16) == [(0, 10, 6.0)]
+    assert O.unit_events(rho, 3.5, 16) == [(0, 10, 6.0), (2, 40, 4.0)]
+    assert O.unit_events(rho, 7.0, 16) == []
+
+
+def test_unit_events_merge_across_a_window_edge():
+    W = 16
+    rho = np.zeros(64)
+    rho[15], rho[16] = 8.0, 7.0      # one signal split by the edge at 16: only j = 15 survives
+    rho[47], rho[48] = 5.0, 9.0      # the later sample wins here
+    assert O.unit_events(rho, 4.0, W) == [(0, 15, 8.0), (3, 48, 9.0)]
+    # farther apart than W: both windows keep their winners
+    rho2 = np.zeros(64)
+    rho2[2], rho2[30] = 8.0, 7.0
+    assert O.unit_events(rho2, 4.0, W) == [(0, 2, 8.0), (1, 30, 7.0)]
+    # equal values within W: the lower index survives; lowest index inside a window on ties
+    rho3 = np.zeros(64)
+    rho3[20], rho3[25], rho3[33] = 6.0, 6.0, 6.0
+    assert O.unit_events(rho3, 4.0, W) == [(1, 20, 6.0)]
+
+
+def test_unit_events_properties_on_noise():
+    rng = np.random.default_rng(11)
+    W = 32
+    for _ in range(20):
+        rho = np.abs(rng.standard_normal(1024) + 1j * rng.standard_normal(1024))
+        ev = O.unit_events(rho, 2.5, W)
+        js, vals = O.window_maxima(rho, W)
+        for (w, j, v) in ev:
+            seg = rho[w * W: (w + 1) * W]
+            assert v == seg.max() and j == w * W + int(np.argmax(seg)) and v >= 2.5
+        # kept events are more than W apart; a dropped window winner above threshold is
+        # beaten by an adjacent winner within W
+        ej = [j for (_, j, _) in ev]
+        assert all(b - a > W for a, b in zip(ej, ej[1:]))
+        kept = {w for (w, _, _) in ev}
+        for w in range(len(js)):
+            if vals[w] >= 2.5 and w not in kept:
+                assert any(0 <= w2 < len(js) and abs(js[w2] - js[w]) <= W and
+                           (vals[w2] > vals[w] or (vals[w2] == vals[w] and js[w2] < js[w])) for w2 in (w - 1, w + 1))
+
+
+def test_segment_events_pick_loudest_template_then_merge():
+    n, W = 64, 16
+    ev = {0: [(0, 3, 6.0), (2, 40, 5.0)],
+          1: [(0, 5, 7.0), (3, 49, 6.0)],
+          2: [(2, 41, 5.0)]}
+    # window 0: template 1 (7.0); window 2: tie 5.0 -> template 0; window 3: 6.0 at 49 beats 5.0 at 40
+    assert O.segment_events(ev, n, 4.0, W) == [(0, 1, 5, 7.0), (3, 1, 49, 6.0)]
