@@ -218,6 +218,54 @@ def run_gpu(args):
                 "pass1": {"ms": ms[0], "launches": nl[0], "units": u1[0]},
                 "chisq_at_peaks_median": float(np.median(chi))}
 
+    def measure_events(prec: str, steps: int, threshold: float, log2w: int, p_bands: int):
+        """Events path: filter + clustering, then chi^2 at the segment events."""
+        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        _, P = mf.psd(grid, prefix=True, device=dev)
+        st = S64 if prec == "fp64" else S32
+        ws = torch.empty(mf.filter_events_workspace_bytes(grid, prec, bank.n_tmpl, n_seg, log2w), dtype=torch.uint8,
+                         device=dev)
+
+        def step():
+            r = mf.filter_events(grid, bank, st, Sn, prec, threshold=threshold, log2_window=log2w, workspace=ws)
+            c, _ = mf.chisq_events(grid, bank, st, Sn, P, r["seg_events"], prec, p_bands=p_bands)
+            return r, c
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res, chi = step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = res["seg_events"]
+        t, j, rho = ev["t"].cpu().numpy(), ev["j"].cpu().numpy(), ev["rho"].cpu().numpy()
+        chi = chi.cpu().numpy()
+        recs = {(s_, w): (int(t[s_, w]), int(j[s_, w]), float(rho[s_, w]), float(chi[s_, w]))
+                for s_ in range(t.shape[0]) for w in range(t.shape[1]) if t[s_, w] >= 0}
+        return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl * n_seg, "events": recs}
+
+    def measure_n4m(prec: str, steps: int):
+        """The filter on 4 x 2^20-sample segments (1024 s at 4096 Hz), same bank."""
+        g4 = mf.Grid(wl.n * 4, wl.fs, wl.f_low)
+        Sn4 = mf.psd(g4, device=dev)
+        S4h = Sn4.cpu().numpy()
+        s4 = synth.coloured_noise(S4h[g4.k_lo: g4.n // 2], g4.df, g4.k_lo, g4.n // 2 + 1, synth.rngs(cfg, 1)[0],
+                                  dtype=np.complex64 if prec != "fp64" else np.complex128)
+        st4 = torch.from_numpy(s4[None]).to(dev)
+        bank = mf.spa_bank(g4, mc, eta, Sn4, prec)
+        ws = torch.empty(mf.filter_workspace_bytes(g4, prec, bank.n_tmpl, 1), dtype=torch.uint8, device=dev)
+        peaks = torch.empty(2 * bank.n_tmpl, dtype=torch.float64, device=dev)
+        mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        del ws
+        return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl, "n": g4.n,
+                "plan": mf.filter_plan(g4, prec)}
+
     main = measure(args.precision, args.steps, args.warmup, args.timing_stride)
     fp64 = None
     if args.fp64_steps > 0:
@@ -225,7 +273,14 @@ def run_gpu(args):
     chisq = None
     if args.chisq_steps > 0:
         chisq = measure_chisq(args.precision, args.chisq_steps, 1, args.timing_stride, args.chisq_bands)
-    return main, fp64, chisq
+    events = None
+    if args.events_steps > 0:
+        e32 = measure_events(args.precision, args.events_steps, args.events_threshold, args.events_log2w,
+                             args.chisq_bands)
+        e64 = measure_events("fp64", 1, args.events_threshold, args.events_log2w, args.chisq_bands)
+        events = (e32, e64)
+    n4m = measure_n4m(args.precision, args.n4m_steps) if args.n4m_steps > 0 else None
+    return main, fp64, chisq, events, n4m
 
 
 def run_refine(args):
@@ -360,6 +415,10 @@ def main():
     ap.add_argument("--refine-steps", type=int, default=20)
     ap.add_argument("--chisq-steps", type=int, default=5)
     ap.add_argument("--chisq-bands", type=int, default=16)
+    ap.add_argument("--events-steps", type=int, default=3)
+    ap.add_argument("--events-threshold", type=float, default=4.0)
+    ap.add_argument("--events-log2w", type=int, default=11)
+    ap.add_argument("--n4m-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -377,7 +436,7 @@ def main():
         print(f"[bench] cpu baseline {cpu['value']:.2f} {UNIT} on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     print(f"[bench] gpu workload {wl.name} precision {args.precision}", file=sys.stderr, flush=True)
-    m, fp64, chisq = run_gpu(args)
+    m, fp64, chisq, events, n4m = run_gpu(args)
     khash = kernel_hash()
     value = m["units"] / (m["ms_per_step"] * 1e-3)
     eff_gbs = m["b_alg_unit"] * m["units"] / (m["ms_per_step"] * 1e-3) / 1e9
@@ -414,6 +473,27 @@ def main():
             "chisq_at_peaks_median": round(chisq["chisq_at_peaks_median"], 3),
             "plan": chisq["plan"],
             "roofline": chisq_roofline(chisq, wl, khash)}
+    if events is not None:
+        e32, e64 = events
+        a, b = e32["events"], e64["events"]
+        both = [k for k in a if k in b and a[k][:2] == b[k][:2]]
+        drho = np.array([abs(a[k][2] / b[k][2] - 1.0) for k in both]) if both else np.zeros(0)
+        dchi = np.array([abs(a[k][3] / b[k][3] - 1.0) for k in both if b[k][3] != 0.0]) if both else np.zeros(0)
+        line["events_path"] = {
+            "value": round(e32["units"] / (e32["ms_per_step"] * 1e-3), 1), "unit": UNIT,
+            "ms_per_step": round(e32["ms_per_step"], 4), "steps": e32["steps"],
+            "threshold": args.events_threshold, "window_samples": 1 << args.events_log2w,
+            "events": len(a), "chisq_p_bands": args.chisq_bands,
+            "accuracy_vs_fp64": {"matched": len(both), "fp32_only": len(a) - len(both), "fp64_only": len(b) - len(both),
+                                 "rho_within_0.03pct": round(float(np.mean(drho < 3e-4)), 5) if both else None,
+                                 "chisq_within_0.5pct": round(float(np.mean(dchi < 5e-3)), 5) if both else None,
+                                 "rho_max_rel_err": float(drho.max()) if both else None,
+                                 "chisq_max_rel_err": float(dchi.max()) if dchi.size else None}}
+    if n4m is not None:
+        v4 = n4m["units"] / (n4m["ms_per_step"] * 1e-3)
+        line["n4m_path"] = {"value": round(v4, 1), "unit": UNIT, "n": n4m["n"], "ms_per_step": round(n4m["ms_per_step"], 4),
+                            "steps": n4m["steps"], "samples_per_s": round(v4 * n4m["n"], 1),
+                            "samples_per_s_vs_2e20": round(v4 * n4m["n"] / (value * wl.n), 4), "plan": n4m["plan"]}
     print(json.dumps(line), flush=True)
 
 

@@ -26,7 +26,8 @@ from . import _lib as L
 __all__ = ["Grid", "Bank", "psd", "spa_bank", "filter", "filter_plan", "filter_workspace_bytes", "ifft", "snr_sq", "SnrSq",
            "PRECISIONS", "version",
            "template_metric", "chisq", "filter_chisq", "filter_chisq_workspace_bytes",
-           "psd_prefix", "rfft", "filter_events", "chisq_events", "filter_chisq_plan"]
+           "psd_prefix", "rfft", "filter_events", "chisq_events", "filter_chisq_plan",
+           "filter_events_workspace_bytes"]
 
 PRECISIONS = {"fp64": L.MF_FP64, "fp32_ph64": L.MF_FP32_PH64, "fp32": L.MF_FP32}
 SIGMA_MODES = {"fp64": L.MF_SIGMA_FP64, "comp32": L.MF_SIGMA_COMP32}
@@ -307,6 +308,15 @@ def _events_view(raw: torch.Tensor, shape):
     return {"rho": ev[..., 0], "j": ints[..., 0], "t": ints[..., 1], "raw": raw}
 
 
+def filter_events_workspace_bytes(grid: Grid, precision, n_tmpl: int, n_seg: int, log2_window: int = 12) -> int:
+    g = grid.c()
+    nb = int(_clib.mf_filter_events_workspace_bytes(C.byref(g), _prec(precision), int(n_tmpl), int(n_seg),
+                                                     int(log2_window)))
+    if nb == 0:
+        raise L.MfError(-1, "no events workspace for these arguments (log2_window in [4, min(16, log2 N)])")
+    return nb
+
+
 def filter_events(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, precision="fp32_ph64",
                   threshold: float = 5.5, log2_window: int = 12, unit_events: bool = False,
                   workspace: torch.Tensor | None = None):
@@ -325,9 +335,7 @@ def filter_events(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor
     n_seg = int(stilde.shape[0])
     dev = stilde.device
     g = grid.c()
-    need = int(_clib.mf_filter_events_workspace_bytes(C.byref(g), prec, bank.n_tmpl, n_seg, int(log2_window)))
-    if need == 0:
-        raise L.MfError(-1, "no events workspace for these arguments (log2_window in [4, min(16, log2 N)])")
+    need = filter_events_workspace_bytes(grid, prec, bank.n_tmpl, n_seg, log2_window)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     n_win = grid.n >> int(log2_window)

@@ -7,6 +7,10 @@
 --fetch / --write: `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
 profile_run.py.  The byte counters are scaled by the factor that makes the
 calibration copy kernel read and write exactly --copy-mib MiB.
+--sq: a `rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU ...` run; with --elements
+(kernel=output elements per dispatch, comma-separated) and the kernel trace of
+--stats it writes VALU instructions per element and the VALU issue fraction
+(wave64 instructions x 4 cycles / (duration x 2.4 GHz x 1024 SIMDs)).
 """
 from __future__ import annotations
 
@@ -69,6 +73,9 @@ def main():
     ap.add_argument("--command-stats", default="")
     ap.add_argument("--command-fetch", default="")
     ap.add_argument("--command-write", default="")
+    ap.add_argument("--sq")
+    ap.add_argument("--command-sq", default="")
+    ap.add_argument("--elements", default="")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     khash = kernel_hash()
@@ -107,6 +114,34 @@ def main():
                          f"WRITE_SIZE {w_copy / 1024:.1f} KiB -> scale fetch x{sf:.4f}, write x{sw:.4f}\n")
                 fh.write(f"fetch_bytes_per_launch: {fb:.0f}\nwrite_bytes_per_launch: {wb:.0f}\n")
                 fh.write(f"hbm_bytes_per_launch: {fb + wb:.0f}\n")
+    if args.sq:
+        rows = list(csv.DictReader(open(find(args.sq, "*counter_collection.csv"))))
+        per = {}
+        for r in rows:
+            per.setdefault(short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+        dur = {}
+        if args.stats:
+            for r in csv.DictReader(open(find(args.stats, "*kernel_stats.csv"))):
+                dur[short(r["Name"])] = float(r.get("AverageNs", 0.0))
+        elements = dict(kv.split("=") for kv in args.elements.split(",") if kv)
+        for k, cnt in sorted(per.items()):
+            if k not in elements:
+                continue
+            path = os.path.join(args.out, f"valu_{k}_{args.workload}.txt")
+            with open(path, "w") as fh:
+                fh.write(f"# SQ counters per dispatch of {k}, workload {args.workload}\n")
+                fh.write(f"# command: {args.command_sq}\nkernel_source_hash: {khash}\n")
+                fh.write(f"dispatches: {len(next(iter(cnt.values())))}\n")
+                for name, vals in sorted(cnt.items()):
+                    fh.write(f"{name}: {statistics.mean(vals):.1f}\n")
+                el = float(elements[k])
+                valu = statistics.mean(cnt.get("SQ_INSTS_VALU", [0.0]))
+                fh.write(f"output_elements_per_dispatch: {el:.0f}\n")
+                fh.write(f"valu_instructions_per_element: {valu * 64.0 / el:.2f}\n")
+                if k in dur and dur[k] > 0:
+                    frac = valu * 4.0 / (dur[k] * 1e-9 * 2.4e9 * 1024.0)
+                    fh.write(f"avg_duration_us: {dur[k] / 1e3:.2f}\nvalu_issue_fraction: {frac:.3f}\n")
     print("written to", args.out)
 
 
