@@ -1,12 +1,15 @@
 // chi^2 time-frequency veto of arXiv:0906.4175, Eq. (5) (Sec. 1.2), evaluated
-// at each (template, segment) unit's peak sample j:
+// at single samples j: each unit's peak, or listed events (template t,
+// segment s, sample j):
 //   z_l(j) = 4 df sum_{k in band l} conj(h_k) s_k / S_k e^{2 pi i j k / N}
 //   chi^2  = p / sigma^2 sum_l |z_l - z / p|^2 = p / sigma^2 (sum_l |z_l|^2 - |z|^2 / p),
 // using sum_l z_l = z.  The p bands split the template's band into equal
 // shares of sigma^2 (Eq. (4)); a bin belongs to the band in which the sum of
 // f^{-7/3}/S over the bins before it falls.  Band edges come from binary
-// searches in the FP64 prefix sums of mf_psd.  One work-group per unit; FP64
-// phase (the time shift j k / N is reduced exactly in integers), FP64 sums.
+// searches in the FP64 prefix sums of mf_psd.  One work-group per sample;
+// FP64 phase (the time shift j k / N is reduced exactly in integers) and FP64
+// sums; for FP32 data the weight and the rotor of the reduced phase are FP32
+// (hardware sine and cosine of a fraction of a cycle), as in the filter.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -89,26 +92,35 @@ __global__ void __launch_bounds__(NT) k_chisq(int64_t n, double df, const mf_ban
     }
     __syncthreads();
     const PhaseCoef pc = load_coef(e);
-    const double amp0 = pow(df, -7.0 / 6.0);
+    const double c4 = 4.0 * df * pow(df, -7.0 / 6.0);  // 4 df f^{-7/6} = c4 k^{-7/6}
     const cx<T>* sp = stilde + s * (n / 2 + 1);
     for (int l = 0; l < p; ++l) {
         double ar = 0.0, ai = 0.0;
         for (int64_t k = edge[l] + tid; k < edge[l + 1]; k += NT) {
             const double kd = (double)k;
-            const double u3 = inv_cbrt_f64_full(kd);
-            double ph = spa_cycles_f64(pc, kd);
+            const double u = inv_cbrt_f64_full(kd);  // k^{-1/3}
+            const double uu = u * u;
+            double ph = fma(u, fma(u, fma(u, fma(uu, pc.b5, pc.b3), pc.b2), pc.b1), pc.c0);
             ph -= rint(ph);
-            double sh = (double)((j * k) % n) / (double)n;  // exact fraction of a cycle
-            ph += sh;
+            ph += (double)((j * k) & (n - 1)) / (double)n;  // time shift, exact (n is a power of two)
             ph -= rint(ph);
-            double sn, cs;
-            sincospi(2.0 * ph, &sn, &cs);
-            const double a = amp0 * u3 * u3 * u3 * sqrt(u3);
-            const double g = 4.0 * df * a / Sn[k];
             const cx<T> sv = sp[k];
-            const double wr = (double)sv.x * g, wi = (double)sv.y * g;
-            ar += wr * cs - wi * sn;
-            ai += wr * sn + wi * cs;
+            if constexpr (sizeof(T) == 4) {
+                // FP32 data: FP32 weight and hardware rotor of the reduced FP64 phase
+                const float uf = (float)u;
+                const float g = (float)c4 * uf * uf * uf * sqrtf(uf) / (float)Sn[k];
+                const cx<float> rot = rotor_rev((float)ph);
+                const float wr = sv.x * g, wi = sv.y * g;
+                ar += (double)(wr * rot.x - wi * rot.y);
+                ai += (double)(wr * rot.y + wi * rot.x);
+            } else {
+                double sn, cs;
+                sincospi(2.0 * ph, &sn, &cs);
+                const double g = c4 * u * uu * sqrt(u) / Sn[k];
+                const double wr = sv.x * g, wi = sv.y * g;
+                ar += wr * cs - wi * sn;
+                ai += wr * sn + wi * cs;
+            }
         }
         ar = block_sum<NT>(ar, scratch);
         ai = block_sum<NT>(ai, scratch);
@@ -136,7 +148,7 @@ hipError_t launch_chisq(int64_t n, double fs, mf_precision prec, const mf_bank_e
                         const mf_peak* peaks, const mf_event* events, int64_t n_per_seg, double* chisq, double* rho,
                         hipStream_t s) {
     const double df = fs / (double)n;
-    constexpr int NT = 256;
+    constexpr int NT = 512;
     const unsigned blocks = (unsigned)(events ? n_seg * n_per_seg : n_tmpl * n_seg);
     if (prec == MF_FP64)
         hipLaunchKernelGGL((k_chisq<double, NT>), dim3(blocks), dim3(NT), 0, s, n, df, bank, n_tmpl, n_seg,

@@ -9,7 +9,8 @@
 //  * template clustering, per segment: each window's loudest unit event
 //    across templates (ties: lowest template index), kept under the same
 //    adjacent-window rule.
-// One thread per (unit or segment, window); deterministic, no atomics.
+// One thread per (unit or segment, window), one wave per segment window for
+// the template maximum; deterministic, no atomics.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -76,17 +77,36 @@ __global__ void k_events_unit(const unsigned long long* keys, int64_t n_tmpl, in
     }
 }
 
-// loudest unit event of each (segment, window) across templates
-__global__ void k_events_best(const mf_event* unit_ev, int64_t n_tmpl, int64_t n_seg, int64_t n_win, mf_event* best) {
+// e beats b: an event against none, a larger rho, or an equal rho of a lower template
+__device__ __forceinline__ bool louder(const mf_event& e, const mf_event& b) {
+    if (e.t < 0) return false;
+    if (b.t < 0) return true;
+    return e.rho > b.rho || (e.rho == b.rho && e.t < b.t);
+}
+
+// loudest unit event of each (segment, window) across templates: one 64-lane
+// wave per (segment, window), lanes stride over the templates
+__global__ void __launch_bounds__(256) k_events_best(const mf_event* unit_ev, int64_t n_tmpl, int64_t n_seg,
+                                                     int64_t n_win, mf_event* best) {
     const int64_t total = n_seg * n_win;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < total; i += waves) {
         const int64_t s = i / n_win, w = i % n_win;
         mf_event b{0.0, -1, -1};
-        for (int64_t t = 0; t < n_tmpl; ++t) {
+        for (int64_t t = lane; t < n_tmpl; t += 64) {
             const mf_event e = unit_ev[(t * n_seg + s) * n_win + w];
-            if (e.t >= 0 && (b.t < 0 || e.rho > b.rho)) b = e;
+            if (louder(e, b)) b = e;
         }
-        best[i] = b;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            mf_event o;
+            o.rho = __shfl_xor(b.rho, off, 64);
+            o.j = __shfl_xor(b.j, off, 64);
+            o.t = __shfl_xor(b.t, off, 64);
+            if (louder(o, b)) b = o;
+        }
+        if (lane == 0) best[i] = b;
     }
 }
 
@@ -129,8 +149,9 @@ hipError_t launch_events(const unsigned long long* keys, int64_t n_tmpl, int64_t
                        n_win, log2w, f64, bank, unit_ev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_events_best, dim3(cover(n_seg * n_win)), dim3(256), 0, s, unit_ev, n_tmpl, n_seg, n_win,
-                       best);
+    const int64_t wave_blocks = (n_seg * n_win + 3) / 4;  // four waves per block
+    hipLaunchKernelGGL(k_events_best, dim3((unsigned)(wave_blocks > 65536 ? 65536 : wave_blocks)), dim3(256), 0, s,
+                       unit_ev, n_tmpl, n_seg, n_win, best);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_events_merge, dim3(cover(n_seg * n_win)), dim3(256), 0, s, best, n_seg, n_win, log2w,

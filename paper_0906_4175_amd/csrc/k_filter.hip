@@ -138,9 +138,10 @@ static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 102
     X(float, 32, 32, 16, 32) X(float, 32, 64, 16, 32) X(float, 64, 64, 16, 64) X(float, 64, 128, 16, 32)  \
     X(float, 128, 128, 16, 32) X(float, 128, 256, 16, 16) X(float, 256, 256, 16, 16)                       \
     X(float, 256, 512, 16, 8) X(float, 512, 512, 16, 8) X(float, 512, 1024, 16, 4)                          \
-    X(float, 256, 4096, 16, 1) X(float, 1024, 2048, 16, 2) X(float, 2048, 2048, 8, 2)                       \
+    X(float, 256, 4096, 16, 1) X(float, 1024, 2048, 16, 2) X(float, 1024, 4096, 8, 1)                       \
     X(float, 1024, 1024, 8, 4) X(float, 1024, 1024, 16, 8) X(float, 1024, 1024, 16, 4)                      \
-    X(float, 512, 2048, 16, 2) X(float, 2048, 512, 8, 8)                                                    \
+    X(float, 512, 2048, 16, 2) X(float, 2048, 512, 8, 8) X(float, 2048, 2048, 8, 2) X(float, 1024, 4096, 16, 1) \
+    X(float, 512, 8192, 16, 1)                                                                              \
     X(double, 32, 32, 8, 32) X(double, 32, 64, 8, 32) X(double, 64, 64, 8, 64) X(double, 64, 128, 8, 32)   \
     X(double, 128, 128, 8, 32) X(double, 128, 256, 8, 16) X(double, 256, 256, 8, 16)                        \
     X(double, 256, 512, 8, 8) X(double, 512, 512, 8, 8) X(double, 512, 1024, 8, 4)                          \

@@ -534,10 +534,12 @@ def test_chisq_at_peaks_matches_oracle(mf, prec, p):
     chi2, rho = mf.chisq(g, bank, st, Sn, P, res, prec, p_bands=p)
     chi2, rho = chi2.cpu().numpy(), rho.cpu().numpy()
     js = res["j"].cpu().numpy()
+    # FP64 data: FP64 throughout; FP32 data: FP32 weights and rotors, FP64 phase and sums
+    tol, rtol = (1e-9, 1e-10) if prec == "fp64" else (1e-5, 1e-6)
     for t in range(len(mc)):
         c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], s, Sn_ref, int(js[t, 0]), p)
-        assert abs(chi2[t, 0] - c_ref) <= 1e-9 * (c_ref + r_ref ** 2), (t, chi2[t, 0], c_ref)
-        assert rho[t, 0] == pytest.approx(r_ref, rel=1e-10)
+        assert abs(chi2[t, 0] - c_ref) <= tol * (c_ref + r_ref ** 2 + 1.0), (t, chi2[t, 0], c_ref)
+        assert rho[t, 0] == pytest.approx(r_ref, rel=rtol)
         # the filter's own peak value agrees to its precision class
         assert float(res["rho"][t, 0]) == pytest.approx(r_ref, rel=1e-9 if prec == "fp64" else 1e-4)
 
@@ -567,7 +569,7 @@ def test_chisq_vetoes_a_glitch_full_size(mf):
     assert chi2[0, 1] > 5.0 * (2 * p - 2)          # the loud mismatched signal
     for t, sgi in [(0, 0), (1, 1)]:
         c_ref, r_ref = _chisq_ref(n, fs, mc[t], eta[t], segs[sgi], Sn_ref, int(js[t, sgi]), p)
-        assert abs(chi2[t, sgi] - c_ref) <= 1e-9 * (c_ref + r_ref ** 2)
+        assert abs(chi2[t, sgi] - c_ref) <= 1e-5 * (c_ref + r_ref ** 2 + 1.0)
 
 
 # ---------------------------------------------------------------------------
