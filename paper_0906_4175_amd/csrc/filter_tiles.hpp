@@ -44,15 +44,13 @@ __host__ __device__ constexpr int tw_total(int L) { return tw_offset(L, num_stag
 
 template <typename T, int L>
 __device__ __forceinline__ void fill_stage_twiddles(cx<T>* tw, int tid, int nt) {
-    constexpr int NS = num_stages(L);
-    for (int m = tid; m < tw_total(L); m += nt) {
-        int s = 1;
-#pragma unroll
-        for (int i = 2; i < NS; ++i) s = m >= tw_offset(L, i) ? i : s;
-        const int k = m - tw_offset(L, s);
-        const int M = span_before(L, s) * radix_at(L, s);
-        tw[m] = root_of_unity((T)k / (T)M);
-    }
+    static_for<1, num_stages(L)>([&](auto S_) {
+        constexpr int s = decltype(S_)::value;
+        constexpr int SPAN = span_before(L, s);
+        constexpr int OFF = tw_offset(L, s);
+        constexpr T INV_M = (T)1 / (T)(SPAN * radix_at(L, s));  // a power of two: exact
+        for (int k = tid; k < SPAN; k += nt) tw[OFF + k] = root_of_unity((T)k * INV_M);
+    });
 }
 
 // p[r] = w^r for r = 0..R-1 by a binary tree of products (depth log2 r).
@@ -242,8 +240,9 @@ struct Pass2 {
     static constexpr int NWAVE = NT / 64;
     static constexpr int TW = tw_total(N2);
     static constexpr bool F64 = std::is_same<T, double>::value;
+    static constexpr int R0 = radix_at(N2, 0);
     static constexpr size_t SMEM =
-        (size_t)(B * PN2 + TW + B * NS) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
+        (size_t)(B * PN2 + TW + B * NS + B * R0) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
 
     // LDS element offset of padded index x + r * step when x's padding is known
@@ -260,7 +259,8 @@ struct Pass2 {
         cx<T>* buf = (cx<T>*)smem;
         cx<T>* tw = buf + B * PN2;
         cx<T>* trow = tw + TW;  // [B][NS]: t^{weight_s} per row
-        unsigned long long* red_key = (unsigned long long*)(trow + B * NS);
+        cx<T>* pow0 = trow + B * NS;  // [B][R0]: (t^{weight_0})^r, the stage-0 factors of each row
+        unsigned long long* red_key = (unsigned long long*)(pow0 + B * R0);
         double* red_zz = (double*)(red_key + NWAVE);
         int* red_j = (int*)(red_zz + NWAVE);
         unsigned int* red_cnt = (unsigned int*)(red_j + NWAVE);
@@ -273,6 +273,12 @@ struct Pass2 {
             const int b = tid / NS, st = tid % NS;
             const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st);  // < N
             trow[b * NS + st] = root_of_unity((T)m / (T)N);
+        }
+        for (int q = tid; q < B * R0; q += NT) {
+            // each power from its exactly reduced argument (no product chain)
+            const int b = q / R0, r = q % R0;
+            const int64_t m = ((int64_t)(rb * B + b) * digit_weight(N2, 0) * r) & (N - 1);
+            pow0[q] = root_of_unity((T)m / (T)N);
         }
 
         T thr2 = T(0);
@@ -313,22 +319,23 @@ struct Pass2 {
                 if (NBF % NT == 0 || bf < NBF) {
                     const int j = bf % PER_ROW;
                     const int b = bf / PER_ROW;
-                    cx<T> base = trow[b * NS + s];
                     if constexpr (s == 0) {
                         const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
 #pragma unroll
                         for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
+                        // stage 0 has no stage twiddle: its factors are the row's table
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pow0[b * R0 + r]);
                     } else {
                         const int k = j % NSPAN;
                         const cx<T>* src = buf + b * PN2;
 #pragma unroll
                         for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
-                        base = cmul(tw[tw_offset(N2, s) + k], base);
-                    }
-                    cx<T> p[R];
-                    powers<R>(base, p);
+                        cx<T> p[R];
+                        powers<R>(cmul(tw[tw_offset(N2, s) + k], trow[b * NS + s]), p);
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
+                        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
+                    }
                     IDft<R, T>::run(v[i]);
                 }
             }
