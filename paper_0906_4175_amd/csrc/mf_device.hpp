@@ -100,14 +100,43 @@ struct IDft<4, T> {
     }
 };
 
+// Butterfly (e + w a, e - w a) with w = (+-1 +- i)/sqrt(2) (16th-root index q
+// = 2, 6, 10, 14): w a = h (sx, sy) with sx, sy signed sums of a.x and a.y, so
+// each output component is one add and one fused multiply-add.
+template <int Q, typename T>
+__device__ __forceinline__ void butterfly_diag(cx<T> e, cx<T> a, cx<T>& lo, cx<T>& hi) {
+    constexpr T h = T(0.70710678118654752);
+    T sx, sy;
+    if constexpr (Q == 2) {
+        sx = a.x - a.y;
+        sy = a.x + a.y;
+    } else if constexpr (Q == 6) {
+        sx = -(a.x + a.y);
+        sy = a.x - a.y;
+    } else if constexpr (Q == 10) {
+        sx = a.y - a.x;
+        sy = -(a.x + a.y);
+    } else {
+        sx = a.x + a.y;
+        sy = a.y - a.x;
+    }
+    lo = cx<T>{fma(sx, h, e.x), fma(sy, h, e.y)};
+    hi = cx<T>{fma(sx, -h, e.x), fma(sy, -h, e.y)};
+}
+
 template <int R, typename T>
 struct IDft {
     template <int U>
     __device__ __forceinline__ static void combine(cx<T>* v, cx<T>* e, cx<T>* o) {
         if constexpr (U < R / 2) {
-            cx<T> t = rot<U, R>(o[U]);
-            v[U] = e[U] + t;
-            v[U + R / 2] = e[U] - t;
+            constexpr int q = (U * 16 / R) % 16;
+            if constexpr (q == 2 || q == 6 || q == 10 || q == 14) {
+                butterfly_diag<q, T>(e[U], o[U], v[U], v[U + R / 2]);
+            } else {
+                cx<T> t = rot<U, R>(o[U]);
+                v[U] = e[U] + t;
+                v[U + R / 2] = e[U] - t;
+            }
             combine<U + 1>(v, e, o);
         }
     }
