@@ -362,7 +362,8 @@ def roofline(m, workload_name: str, khash: str):
     ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     prec = "fp64" if m["prec"] == "fp64" else "fp32"
     fused = bool(m["plan"]["fused"])
-    names = [f"k_step_{prec}"] if fused else [f"k_pass1_{prec}", f"k_pass2_{prec}"]
+    shape = f"{m['plan']['n1']}x{m['plan']['n2']}"
+    names = [f"k_step_{prec}_{shape}"] if fused else [f"k_pass1_{prec}_{shape}", f"k_pass2_{prec}_{shape}"]
     rec = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "+".join(names),
            "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": round(bytes_per_launch),
@@ -392,7 +393,7 @@ def chisq_roofline(c, wl, khash: str):
     ach = flops_unit * units_per_launch / (avg_ms * 1e-3) / 1e12
     peak = FP64_VALU_PEAK_TFLOPS if c["prec"] == "fp64" else FP32_VALU_PEAK_TFLOPS
     prec = "fp64" if c["prec"] == "fp64" else "fp32"
-    name = f"k_pass2_band_{prec}"
+    name = f"k_pass2_band_{prec}_{n1}x{n2}"
     tb = read_traffic(name, wl.name, khash)
     return {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
             "traffic": round(tb) if tb is not None else None, "kernel": name, "avg_launch_ms": round(avg_ms, 4),
