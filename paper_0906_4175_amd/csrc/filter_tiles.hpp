@@ -30,25 +30,27 @@ struct Partial64 {
 
 // Weight of the input-index digit that stage s of an L-point Stockham
 // transform consumes: L / (span * radix).
-__host__ __device__ constexpr int digit_weight(int L, int s) { return L / (span_before(L, s) * radix_at(L, s)); }
+__host__ __device__ constexpr int digit_weight(int L, int s, int maxr = 16) {
+    return L / (span_before(L, s, maxr) * radix_at(L, s, maxr));
+}
 
 // Stage twiddle tables, one contiguous table per stage s >= 1:
 // e^{+2 pi i k / (span_s R_s)} for k < span_s, so that the lanes of a
 // butterfly row read consecutive entries.
-__host__ __device__ constexpr int tw_offset(int L, int s) {
+__host__ __device__ constexpr int tw_offset(int L, int s, int maxr = 16) {
     int off = 0;
-    for (int i = 1; i < s; ++i) off += span_before(L, i);
+    for (int i = 1; i < s; ++i) off += span_before(L, i, maxr);
     return off;
 }
-__host__ __device__ constexpr int tw_total(int L) { return tw_offset(L, num_stages(L)) + 1; }
+__host__ __device__ constexpr int tw_total(int L, int maxr = 16) { return tw_offset(L, num_stages(L, maxr), maxr) + 1; }
 
-template <typename T, int L>
+template <typename T, int L, int MAXR = 16>
 __device__ __forceinline__ void fill_stage_twiddles(cx<T>* tw, int tid, int nt) {
-    static_for<1, num_stages(L)>([&](auto S_) {
+    static_for<1, num_stages(L, MAXR)>([&](auto S_) {
         constexpr int s = decltype(S_)::value;
-        constexpr int SPAN = span_before(L, s);
-        constexpr int OFF = tw_offset(L, s);
-        constexpr T INV_M = (T)1 / (T)(SPAN * radix_at(L, s));  // a power of two: exact
+        constexpr int SPAN = span_before(L, s, MAXR);
+        constexpr int OFF = tw_offset(L, s, MAXR);
+        constexpr T INV_M = (T)1 / (T)(SPAN * radix_at(L, s, MAXR));  // a power of two: exact
         for (int k = tid; k < SPAN; k += nt) tw[OFF + k] = root_of_unity((T)k * INV_M);
     });
 }
@@ -232,15 +234,15 @@ struct Pass1 {
 // twiddle pass is needed and the result is exact (not only up to a phase).
 // The last stage squares |z| and reduces (max |z|^2, lowest index, count).
 // ---------------------------------------------------------------------------
-template <typename T, bool RAW, int N1, int N2, int B, int NT>
+template <typename T, bool RAW, int N1, int N2, int B, int NT, int MAXR = 16>
 struct Pass2 {
     static constexpr int64_t N = (int64_t)N1 * N2;
-    static constexpr int NS = num_stages(N2);
+    static constexpr int NS = num_stages(N2, MAXR);
     static constexpr int PN2 = pad16(N2);
     static constexpr int NWAVE = NT / 64;
-    static constexpr int TW = tw_total(N2);
+    static constexpr int TW = tw_total(N2, MAXR);
     static constexpr bool F64 = std::is_same<T, double>::value;
-    static constexpr int R0 = radix_at(N2, 0);
+    static constexpr int R0 = radix_at(N2, 0, MAXR);
     static constexpr size_t SMEM =
         (size_t)(B * PN2 + TW + B * NS + B * R0) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
@@ -271,13 +273,13 @@ struct Pass2 {
 
         if (tid < B * NS) {
             const int b = tid / NS, st = tid % NS;
-            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st);  // < N
+            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st, MAXR);  // < N
             trow[b * NS + st] = root_of_unity((T)m / (T)N);
         }
         for (int q = tid; q < B * R0; q += NT) {
             // each power from its exactly reduced argument (no product chain)
             const int b = q / R0, r = q % R0;
-            const int64_t m = ((int64_t)(rb * B + b) * digit_weight(N2, 0) * r) & (N - 1);
+            const int64_t m = ((int64_t)(rb * B + b) * digit_weight(N2, 0, MAXR) * r) & (N - 1);
             pow0[q] = root_of_unity((T)m / (T)N);
         }
 
@@ -307,8 +309,8 @@ struct Pass2 {
 
         static_for<0, NS>([&](auto S_) {
             constexpr int s = decltype(S_)::value;
-            constexpr int R = radix_at(N2, s);
-            constexpr int NSPAN = span_before(N2, s);
+            constexpr int R = radix_at(N2, s, MAXR);
+            constexpr int NSPAN = span_before(N2, s, MAXR);
             constexpr int NBF = B * N2 / R;
             constexpr int BPT = (NBF + NT - 1) / NT;
             constexpr int PER_ROW = N2 / R;
@@ -332,14 +334,14 @@ struct Pass2 {
 #pragma unroll
                         for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
                         cx<T> p[R];
-                        powers<R>(cmul(tw[tw_offset(N2, s) + k], trow[b * NS + s]), p);
+                        powers<R>(cmul(tw[tw_offset(N2, s, MAXR) + k], trow[b * NS + s]), p);
 #pragma unroll
                         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
                     }
                     IDft<R, T>::run(v[i]);
                 }
             }
-            if constexpr (s == 0) fill_stage_twiddles<T, N2>(tw, tid, NT);
+            if constexpr (s == 0) fill_stage_twiddles<T, N2, MAXR>(tw, tid, NT);
             if constexpr (s == NS - 1) {
 #pragma unroll
                 for (int i = 0; i < BPT; ++i) {

@@ -83,16 +83,16 @@ __global__ void __launch_bounds__(64) k_band_table(int64_t n, int n2, const mf_b
 // ---------------------------------------------------------------------------
 // Pass 2 tile in band mode: B rows j1 of one unit, all p bands.
 // ---------------------------------------------------------------------------
-template <typename T, int N1, int N2, int B, int NT>
+template <typename T, int N1, int N2, int B, int NT, int MAXR = 16>
 struct Pass2Band {
     static constexpr int64_t N = (int64_t)N1 * N2;
-    static constexpr int NS = num_stages(N2);
+    static constexpr int NS = num_stages(N2, MAXR);
     static constexpr int PN2 = pad16(N2);
     static constexpr int NWAVE = NT / 64;
-    static constexpr int TW = tw_total(N2);
+    static constexpr int TW = tw_total(N2, MAXR);
     static constexpr int HALF = N1 / 2;
-    static constexpr int RL = radix_at(N2, NS - 1);
-    static constexpr int NSPANL = span_before(N2, NS - 1);
+    static constexpr int RL = radix_at(N2, NS - 1, MAXR);
+    static constexpr int NSPANL = span_before(N2, NS - 1, MAXR);
     static constexpr int PER_ROWL = N2 / RL;
     static constexpr int NBFL = B * N2 / RL;
     static constexpr int BPTL = (NBFL + NT - 1) / NT;
@@ -131,7 +131,7 @@ struct Pass2Band {
 
         if (tid < B * NS) {
             const int b = tid / NS, st = tid % NS;
-            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st);  // < N
+            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st, MAXR);  // < N
             trow[b * NS + st] = root_of_unity((T)m / (T)N);
         }
         for (int m = tid; m < B * HALF; m += NT) {
@@ -139,7 +139,7 @@ struct Pass2Band {
             const int64_t jk = (int64_t)(rb * B + b) * k1 % N1;  // exact reduction
             om[m] = root_of_unity((T)jk / (T)N1);
         }
-        fill_stage_twiddles<T, N2>(tw, tid, NT);
+        fill_stage_twiddles<T, N2, MAXR>(tw, tid, NT);
 
         const mf_bank_entry e = a.bank[t];
         const double sigma = e.sigma;
@@ -170,8 +170,8 @@ struct Pass2Band {
             const int r0 = (int)(e0 / N2), r1 = (int)((e1 - 1) / N2);  // r1 < N1/2
             static_for<0, NS>([&](auto S_) {
                 constexpr int s = decltype(S_)::value;
-                constexpr int R = radix_at(N2, s);
-                constexpr int NSPAN = span_before(N2, s);
+                constexpr int R = radix_at(N2, s, MAXR);
+                constexpr int NSPAN = span_before(N2, s, MAXR);
                 constexpr int NBF = B * N2 / R;
                 constexpr int BPT = (NBF + NT - 1) / NT;
                 constexpr int PER_ROW = N2 / R;
@@ -206,7 +206,7 @@ struct Pass2Band {
                             const cx<T>* src = buf + b * PN2;
 #pragma unroll
                             for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
-                            base = cmul(tw[tw_offset(N2, s) + k], base);
+                            base = cmul(tw[tw_offset(N2, s, MAXR) + k], base);
                         }
                         cx<T> pw[R];
                         powers<R>(base, pw);
@@ -329,9 +329,9 @@ __global__ void __launch_bounds__(NT) k_pass1_band(FilterArgs a) {
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int N1, int N2, int B, int NT>
+template <typename T, int N1, int N2, int B, int NT, int R2>
 __global__ void __launch_bounds__(NT) k_pass2_band(FilterArgs a) {
-    using P = Pass2Band<T, N1, N2, B, NT>;
+    using P = Pass2Band<T, N1, N2, B, NT, R2>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
@@ -379,16 +379,18 @@ __global__ void __launch_bounds__(64) k_finalize_band(const PartialChi* part, in
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-// One shape per N and precision (the default shape of the plain filter).
+// One shape per N and precision (the default shape of the plain filter), the
+// first entry for each being the default; R2 is the largest pass-2 stage
+// radix (MF_BAND_R2=8 selects an R2 = 8 entry where one is built).
 #define MF_BAND_SHAPES(X)                                                                                   \
-    X(float, 32, 32, 16, 32) X(float, 32, 64, 16, 32) X(float, 64, 64, 16, 64) X(float, 64, 128, 16, 32)    \
-    X(float, 128, 128, 16, 32) X(float, 128, 256, 16, 16) X(float, 256, 256, 16, 16)                         \
-    X(float, 256, 512, 16, 8) X(float, 512, 512, 16, 8) X(float, 512, 1024, 16, 4)                            \
-    X(float, 256, 4096, 16, 1) X(float, 1024, 2048, 16, 2) X(float, 2048, 2048, 8, 2)                         \
-    X(double, 32, 32, 8, 32) X(double, 32, 64, 8, 32) X(double, 64, 64, 8, 64) X(double, 64, 128, 8, 32)     \
-    X(double, 128, 128, 8, 32) X(double, 128, 256, 8, 16) X(double, 256, 256, 8, 16)                          \
-    X(double, 256, 512, 8, 8) X(double, 512, 512, 8, 8) X(double, 512, 1024, 8, 4)                            \
-    X(double, 512, 2048, 8, 2) X(double, 1024, 2048, 4, 2) X(double, 2048, 2048, 2, 2)
+    X(float, 32, 32, 16, 32, 16) X(float, 32, 64, 16, 32, 16) X(float, 64, 64, 16, 64, 16) X(float, 64, 128, 16, 32, 16)    \
+    X(float, 128, 128, 16, 32, 16) X(float, 128, 256, 16, 16, 16) X(float, 256, 256, 16, 16, 16)                         \
+    X(float, 256, 512, 16, 8, 16) X(float, 512, 512, 16, 8, 16) X(float, 512, 1024, 16, 4, 16)                            \
+    X(float, 256, 4096, 16, 1, 16) X(float, 256, 4096, 16, 1, 8) X(float, 1024, 2048, 16, 2, 16) X(float, 2048, 2048, 8, 2, 16)                         \
+    X(double, 32, 32, 8, 32, 16) X(double, 32, 64, 8, 32, 16) X(double, 64, 64, 8, 64, 16) X(double, 64, 128, 8, 32, 16)     \
+    X(double, 128, 128, 8, 32, 16) X(double, 128, 256, 8, 16, 16) X(double, 256, 256, 8, 16, 16)                          \
+    X(double, 256, 512, 8, 8, 16) X(double, 512, 512, 8, 8, 16) X(double, 512, 1024, 8, 4, 16)                            \
+    X(double, 512, 2048, 8, 2, 16) X(double, 1024, 2048, 4, 2, 16) X(double, 2048, 2048, 2, 2, 16)
 
 static constexpr int band_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024 : x); }
 
@@ -398,18 +400,23 @@ Plan band_plan(int log2n, mf_precision prec) {
     Plan p{};
     p.log2n = -1;
     bool found = false;
-#define MF_BFIRST(T, N1, N2, C, B)                                                                          \
-    if (!found && band_want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n) { \
+    int want_r2 = 16;
+    if (const char* e = getenv("MF_BAND_R2")) want_r2 = atoi(e) == 8 ? 8 : 16;
+    for (int attempt = 0; attempt < 2 && !found; ++attempt, want_r2 = 16) {
+#define MF_BFIRST(T, N1, N2, C, B, R2)                                                                      \
+    if (!found && band_want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n &&  \
+        R2 == want_r2) {                                                                                    \
         p.n1 = N1;                                                                                          \
         p.n2 = N2;                                                                                          \
         p.c1 = C;                                                                                           \
         p.b2 = B;                                                                                           \
         p.nt1 = band_threads(C * N1 / 16);                                                                  \
-        p.nt2 = band_threads(B * N2 / 16);                                                                  \
+        p.nt2 = band_threads(B * N2 / R2);                                                                  \
         p.log2n = log2n;                                                                                    \
         found = true;                                                                                       \
     }
     MF_BAND_SHAPES(MF_BFIRST)
+    }
 #undef MF_BFIRST
     if (!found) return p;
     // About 256 MiB of product and intermediate per batch, so that pass 2
@@ -462,17 +469,17 @@ static hipError_t run_pass1_band(const FilterArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int N1, int N2, int B>
+template <typename T, int N1, int N2, int B, int R2>
 static hipError_t run_pass2_band(const FilterArgs& a, hipStream_t s) {
     static_assert(N1 % B == 0 && B <= N1, "pass-2 rows per work-group must tile N1");
-    constexpr int NT = band_threads(B * N2 / 16);
+    constexpr int NT = band_threads(B * N2 / R2);
     dim3 grid(N1 / B, (unsigned)a.units);
-    hipLaunchKernelGGL((k_pass2_band<T, N1, N2, B, NT>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_pass2_band<T, N1, N2, B, NT, R2>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_pass1_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s) {
-#define MF_BP1(T, N1, N2, C, B)                                                                                 \
+#define MF_BP1(T, N1, N2, C, B, R2)                                                                             \
     if (band_want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C &&          \
         p.b2 == B) {                                                                                          \
         if (std::is_same<T, float>::value && prec == MF_FP32) return run_pass1_band<float, 1, N1, N2, C>(a, s); \
@@ -484,10 +491,10 @@ hipError_t launch_pass1_band(const Plan& p, mf_precision prec, const FilterArgs&
 }
 
 hipError_t launch_pass2_band(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s) {
-#define MF_BP2(T, N1, N2, C, B)                                                                        \
+#define MF_BP2(T, N1, N2, C, B, R2)                                                                    \
     if (band_want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && \
-        p.b2 == B)                                                                                   \
-        return run_pass2_band<T, N1, N2, B>(a, s);
+        p.b2 == B && p.nt2 == band_threads(B * N2 / R2))                                             \
+        return run_pass2_band<T, N1, N2, B, R2>(a, s);
     MF_BAND_SHAPES(MF_BP2)
 #undef MF_BP2
     return hipErrorInvalidValue;

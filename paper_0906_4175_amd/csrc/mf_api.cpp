@@ -162,19 +162,24 @@ Plan select_plan(int log2n, mf_precision prec) {
     }
     if (const char* e = getenv("MF_PLAN")) {
         Plan q = p;
-        int n1 = 0, n2 = 0, c1 = 0, b2 = 0;
-        if (sscanf(e, "%d,%d,%d,%d", &n1, &n2, &c1, &b2) == 4 && (int64_t)n1 * n2 == (int64_t(1) << log2n)) {
+        int n1 = 0, n2 = 0, c1 = 0, b2 = 0, r2 = 16;
+        const int got = sscanf(e, "%d,%d,%d,%d,%d", &n1, &n2, &c1, &b2, &r2);
+        if (got >= 4 && (int64_t)n1 * n2 == (int64_t(1) << log2n) && (r2 == 8 || r2 == 16)) {
             q.n1 = n1;
             q.n2 = n2;
             q.c1 = c1;
             q.b2 = b2;
             q.nt1 = c1 * n1 / 16 < 64 ? 64 : (c1 * n1 / 16 > 1024 ? 1024 : c1 * n1 / 16);
-            q.nt2 = b2 * n2 / 16 < 64 ? 64 : (b2 * n2 / 16 > 1024 ? 1024 : b2 * n2 / 16);
+            q.nt2 = b2 * n2 / r2 < 64 ? 64 : (b2 * n2 / r2 > 1024 ? 1024 : b2 * n2 / r2);
             q.fused = false;
             if (plan_supported(q, prec)) p = q;
         }
     }
-    if (const char* e = getenv("MF_FUSED")) p.fused = e[0] == '1' && p.nt1 == p.nt2;
+    if (const char* e = getenv("MF_FUSED")) {
+        const int b16 = p.b2 * p.n2 / 16;
+        const int nt16 = b16 < 64 ? 64 : (b16 > 1024 ? 1024 : b16);
+        p.fused = e[0] == '1' && p.nt1 == p.nt2 && p.nt2 == nt16;
+    }
     if (const char* e = getenv("MF_UNITS")) {
         const long v = strtol(e, nullptr, 10);
         if (v >= 1 && v <= 4096) p.units = (int)v;
@@ -247,14 +252,19 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     q.n2 = plan[1];
     q.c1 = plan[2];
     q.b2 = plan[3];
-    q.nt1 = q.c1 * q.n1 / 16 < 64 ? 64 : (q.c1 * q.n1 / 16 > 1024 ? 1024 : q.c1 * q.n1 / 16);
-    q.nt2 = q.b2 * q.n2 / 16 < 64 ? 64 : (q.b2 * q.n2 / 16 > 1024 ? 1024 : q.b2 * q.n2 / 16);
+    auto clampt = [](long long x) { return (int)(x < 64 ? 64 : (x > 1024 ? 1024 : x)); };
+    q.nt1 = clampt((long long)q.c1 * q.n1 / 16);
+    // pass-2 threads select the largest stage radix: B N2 / 16 (default) or B N2 / 8
+    const int nt16 = clampt((long long)q.b2 * q.n2 / 16), nt8 = clampt((long long)q.b2 * q.n2 / 8);
+    q.nt2 = plan[5] == nt8 ? nt8 : nt16;
     q.units = plan[6];
     q.fused = plan[7] != 0;
     if ((int64_t)q.n1 * q.n2 != grid->n || !mf::plan_supported(q, prec))
-        return fail(MF_E_UNSUPPORTED, "plan %dx%d c=%d b=%d is not built for this N/precision", q.n1, q.n2, q.c1, q.b2);
+        return fail(MF_E_UNSUPPORTED, "plan %dx%d c=%d b=%d (pass-2 threads %d) is not built for this N/precision",
+                    q.n1, q.n2, q.c1, q.b2, q.nt2);
     if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
-    if (q.fused && q.nt1 != q.nt2) return fail(MF_E_UNSUPPORTED, "pipelined step needs equal work-group sizes");
+    if (q.fused && (q.nt1 != q.nt2 || q.nt2 != nt16))
+        return fail(MF_E_UNSUPPORTED, "pipelined step needs equal work-group sizes and radix-16 row stages");
     mf::g_plans[{l, prec == MF_FP64}] = q;
     return ok();
 }

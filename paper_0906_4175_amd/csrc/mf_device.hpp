@@ -153,21 +153,21 @@ struct IDft {
     }
 };
 
-// Radix of stage s for an L-point transform: 16 while at least 16 remains,
-// then the remainder.
-__host__ __device__ constexpr int radix_at(int L, int s) {
+// Radix of stage s for an L-point transform: maxr (16 or 8) while at least
+// maxr remains, then the remainder.
+__host__ __device__ constexpr int radix_at(int L, int s, int maxr = 16) {
     int rem = L;
-    for (int i = 0; i < s; ++i) rem /= (rem >= 16 ? 16 : rem);
-    return rem >= 16 ? 16 : rem;
+    for (int i = 0; i < s; ++i) rem /= (rem >= maxr ? maxr : rem);
+    return rem >= maxr ? maxr : rem;
 }
-__host__ __device__ constexpr int num_stages(int L) {
+__host__ __device__ constexpr int num_stages(int L, int maxr = 16) {
     int n = 0;
-    for (int rem = L; rem > 1; rem /= (rem >= 16 ? 16 : rem)) ++n;
+    for (int rem = L; rem > 1; rem /= (rem >= maxr ? maxr : rem)) ++n;
     return n;
 }
-__host__ __device__ constexpr int span_before(int L, int s) {
+__host__ __device__ constexpr int span_before(int L, int s, int maxr = 16) {
     int ns = 1;
-    for (int i = 0; i < s; ++i) ns *= radix_at(L, i);
+    for (int i = 0; i < s; ++i) ns *= radix_at(L, i, maxr);
     return ns;
 }
 __host__ __device__ constexpr int ilog2(long long x) {

@@ -903,3 +903,63 @@ def test_events_accuracy_statistic_fp32_vs_fp64(mf):
     dchi = np.array([abs(e32[k][3] / e64[k][3] - 1.0) for k in both])
     assert np.mean(drho < 3e-4) > 0.99
     assert np.mean(dchi < 5e-3) > 0.99
+
+
+# ---------------------------------------------------------------------------
+# Every built launch plan computes the same thing
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp32_ph64", "fp64"])
+def test_every_candidate_plan_matches_default(mf, prec):
+    """N=2^20, 8 templates, one SNR-20 injection: each candidate shape (both pass-2 radices,
+    separate and pipelined launches, 3 units per batch for ragged batches) against the default."""
+    print(f"[plans] prec={prec}", flush=True)
+    from paper_0906_4175_amd import tune
+    n, fs = 1 << 20, 4096.0
+    inj = dict(m1=1.4, m2=1.4, snr=20.0, j0=654321, phi0=0.3)
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    s, _ = D.segment(n, fs, synth.seed_sequence(21).spawn(1)[0], [inj], dtype=cdt)
+    rng = synth.rngs(21, 1)[0]
+    mc, eta, _, _ = synth.bank_uneven(7, rng)
+    mc = np.append(mc, float(synth.mc_eta(1.4, 1.4)[0]))
+    eta = np.append(eta, 0.25)
+    g = mf.Grid(n, fs)
+    Sn = mf.psd(g)
+    bank = mf.spa_bank(g, mc, eta, Sn, prec)
+    st = torch.from_numpy(s[None]).to(_dev())
+    p = mf.PRECISIONS[prec]
+    ref = mf.filter(g, bank, st, Sn, prec, threshold=6.0)
+    rel = 1e-11 if prec == "fp64" else 2e-5
+    try:
+        for cand in tune.candidates(n, p):
+            tune.set_plan(n, p, dict(cand, units_per_batch=3))
+            got = mf.filter(g, bank, st, Sn, prec, threshold=6.0)
+            assert torch.allclose(got["rho"], ref["rho"], rtol=rel, atol=0), cand
+            loud = ref["rho"] >= 8.0
+            assert torch.equal(got["j"][loud], ref["j"][loud]), cand
+    finally:
+        tune.set_plan(n, p, None)
+    assert int(ref["j"][7, 0]) == inj["j0"]
+
+
+def test_band_mode_radix8_rows_match_radix16(mf):
+    """The band mode with radix-8 row stages (MF_BAND_R2=8) against the default radix 16."""
+    print("[band r2]", flush=True)
+    n, fs = 1 << 20, 4096.0
+    inj = dict(m1=3.0, m2=1.5, snr=15.0, j0=123457, phi0=1.0)
+    s, _ = D.segment(n, fs, synth.seed_sequence(22).spawn(1)[0], [inj], dtype=np.complex64)
+    mc, eta, _, _ = synth.bank_uneven(12, synth.rngs(22, 1)[0])
+    g = mf.Grid(n, fs)
+    Sn, P = mf.psd(g, prefix=True)
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
+    st = torch.from_numpy(s[None]).to(_dev())
+    a = mf.filter_chisq(g, bank, st, Sn, P, "fp32_ph64", series_units=[0, 11])
+    b = _with_env({"MF_BAND_R2": "8"}, lambda: (mf.filter_chisq_plan(g), mf.filter_chisq(
+        g, bank, st, Sn, P, "fp32_ph64", series_units=[0, 11])))
+    assert b[0]["threads_pass2"] == 512
+    b = b[1]
+    assert torch.allclose(b["rho"], a["rho"], rtol=2e-5, atol=0)
+    scale = a["chisq"] + a["rho"] ** 2 + 1.0
+    assert float(((b["chisq"] - a["chisq"]).abs() / scale).max()) < 2e-5
+    sa = a["chisq_series"].double()
+    ra = a["series"].double()
+    assert float(((b["chisq_series"].double() - sa).abs() / (sa + ra ** 2 + 1.0)).max()) < 2e-5
