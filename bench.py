@@ -266,7 +266,47 @@ def run_gpu(args):
         return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl, "n": g4.n,
                 "plan": mf.filter_plan(g4, prec)}
 
+    def measure_graph(prec: str, steps: int):
+        """The same step captured once in a HIP graph and replayed; peaks checked against eager."""
+        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        st = S64 if prec == "fp64" else S32
+        ws = torch.empty(mf.filter_workspace_bytes(grid, prec, bank.n_tmpl, n_seg), dtype=torch.uint8, device=dev)
+        peaks = torch.empty(2 * bank.n_tmpl * n_seg, dtype=torch.float64, device=dev)
+        eager = mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)["raw"].clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # warm-up off the capture stream
+            mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
+        graph.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(peaks, eager))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        same = same and bool(torch.equal(peaks, eager))
+        del graph
+        return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl * n_seg,
+                "peaks_equal_eager": same}
+
+    tuned = None
+    if args.tune:
+        # time every built plan on this workload and install the fastest (untimed)
+        from paper_0906_4175_amd import tune
+        tb = mf.spa_bank(grid, mc, eta, Sn, args.precision)
+        r = tune.tune(grid, tb, S64 if args.precision == "fp64" else S32, Sn, args.precision, units=(32, 64, 128),
+                      steps=2, warmup=1, install=True)
+        tuned = {"plan": r["best"], "ms": round(r["best_ms"], 4), "candidates": len(r["table"])}
+        del tb
     main = measure(args.precision, args.steps, args.warmup, args.timing_stride)
+    main["tuned"] = tuned
+    graph = measure_graph(args.precision, args.graph_steps) if args.graph_steps > 0 else None
     fp64 = None
     if args.fp64_steps > 0:
         fp64 = measure("fp64", args.fp64_steps, 1, args.timing_stride)
@@ -280,7 +320,7 @@ def run_gpu(args):
         e64 = measure_events("fp64", 1, args.events_threshold, args.events_log2w, args.chisq_bands)
         events = (e32, e64)
     n4m = measure_n4m(args.precision, args.n4m_steps) if args.n4m_steps > 0 else None
-    return main, fp64, chisq, events, n4m
+    return main, fp64, chisq, events, n4m, graph
 
 
 def run_refine(args):
@@ -420,6 +460,8 @@ def main():
     ap.add_argument("--events-threshold", type=float, default=4.0)
     ap.add_argument("--events-log2w", type=int, default=11)
     ap.add_argument("--n4m-steps", type=int, default=3)
+    ap.add_argument("--graph-steps", type=int, default=10)
+    ap.add_argument("--tune", action="store_true", help="autotune the launch plan on the workload first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -437,7 +479,7 @@ def main():
         print(f"[bench] cpu baseline {cpu['value']:.2f} {UNIT} on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     print(f"[bench] gpu workload {wl.name} precision {args.precision}", file=sys.stderr, flush=True)
-    m, fp64, chisq, events, n4m = run_gpu(args)
+    m, fp64, chisq, events, n4m, graph = run_gpu(args)
     khash = kernel_hash()
     value = m["units"] / (m["ms_per_step"] * 1e-3)
     eff_gbs = m["b_alg_unit"] * m["units"] / (m["ms_per_step"] * 1e-3) / 1e9
@@ -456,6 +498,7 @@ def main():
         "roofline": roofline(m, wl.name, khash),
         "cpu_baseline": cpu,
         "kernel_source_hash": khash,
+        "autotuned": m.get("tuned"),
     }
     if fp64 is not None:
         v64 = fp64["units"] / (fp64["ms_per_step"] * 1e-3)
@@ -490,6 +533,10 @@ def main():
                                  "chisq_within_0.5pct": round(float(np.mean(dchi < 5e-3)), 5) if both else None,
                                  "rho_max_rel_err": float(drho.max()) if both else None,
                                  "chisq_max_rel_err": float(dchi.max()) if dchi.size else None}}
+    if graph is not None:
+        line["graph_path"] = {"value": round(graph["units"] / (graph["ms_per_step"] * 1e-3), 1), "unit": UNIT,
+                              "ms_per_step": round(graph["ms_per_step"], 4), "steps": graph["steps"],
+                              "peaks_equal_eager": graph["peaks_equal_eager"]}
     if n4m is not None:
         v4 = n4m["units"] / (n4m["ms_per_step"] * 1e-3)
         line["n4m_path"] = {"value": round(v4, 1), "unit": UNIT, "n": n4m["n"], "ms_per_step": round(n4m["ms_per_step"], 4),
