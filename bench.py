@@ -382,7 +382,31 @@ def run_refine(args):
         "fd_check_max_rel": fd_rel, "fd_check_triggers": int(sel.numel()),
         "bin_evaluations_per_s": round(evals_total * n_act / wall, 1),
     }
+    line["roofline"] = refine_roofline(line["bin_evaluations_per_s"], wl_name="gradient-4096trig")
     print(json.dumps(line), flush=True)
+
+
+def refine_roofline(bin_evals_per_s: float, wl_name: str):
+    """ALU roofline of the refinement: bin evaluations/s x the FP32 + FP64 VALU flops of one
+    forward bin evaluation, counted with SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F{32,64} in the committed
+    profile (an adjoint evaluation costs more, so this is a lower bound)."""
+    path = os.path.join(PROFILE_DIR, f"flops_k_snr_grad_fp32_{wl_name}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln and not ln.startswith("#"):
+                k, v = ln.split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        per_bin = float(vals["total_flops_per_element_min"])
+    except (KeyError, ValueError):
+        return None
+    ach = bin_evals_per_s * per_bin / 1e12
+    return {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None, "kernel": "k_snr_grad",
+            "flops_per_bin_evaluation": per_bin, "note": "forward-evaluation flops (lower bound)"}
 
 
 def launches_per_step(m) -> int:

@@ -44,6 +44,9 @@ def main():
     torch.cuda.synchronize()
     del a, b
 
+    if args.workload == 4:
+        run_gradient(args, mf, synth, dev)
+        return
     wl = synth.WORKLOADS[args.workload]
     grid = mf.Grid(wl.n, wl.fs, wl.f_low)
     Sn = mf.psd(grid, device=dev)
@@ -75,6 +78,39 @@ def main():
         torch.cuda.synchronize()
     print(f"profile_run done: copy {args.copy_mib} MiB, {args.steps} steps of {wl.name}, "
           f"max rho {float(res['rho'].max()):.4f}")
+
+
+def run_gradient(args, mf, synth, dev):
+    """ρ² forward, then forward + adjoint, over 4096 triggers (4 times per template
+    of the 1024-template bank, at spread times) of one 2^20 segment; prints the
+    bins each dispatch evaluates (the denominator of per-bin counter figures)."""
+    import torch
+
+    wl = synth.WORKLOADS[2]
+    grid = mf.Grid(wl.n, wl.fs, wl.f_low)
+    Sn = mf.psd(grid, device=dev)
+    Sh = Sn.cpu().numpy()
+    k_lo = grid.k_lo
+    seg = synth.coloured_noise(Sh[k_lo: wl.n // 2], grid.df, k_lo, wl.n // 2 + 1, synth.rngs(4, 1)[0],
+                               dtype=np.complex64)
+    st = torch.from_numpy(seg[None]).to(dev)
+    mc, eta = synth.bank_mc_eta_grid()
+    bank = mf.spa_bank(grid, mc, eta, Sn, "fp32_ph64")
+    reps = 4
+    T = wl.n / wl.fs
+    theta = torch.tensor([[m, e, T * (0.1 + 0.2 * r)] for r in range(reps) for m, e in zip(mc, eta)],
+                         dtype=torch.float64, device=dev)
+    khi = torch.tensor(np.tile(bank.k_hi, reps), dtype=torch.int32, device=dev)
+    segi = torch.zeros(theta.shape[0], dtype=torch.int32, device=dev)
+    bins = int(np.sum(np.tile(bank.k_hi, reps).astype(np.int64) - k_lo + 1))
+    for _ in range(args.steps):
+        F, _, _ = mf.snr_sq(grid, theta, segi, st, Sn, khi)
+    gbar = torch.ones_like(F)
+    for _ in range(args.steps):
+        mf.snr_sq(grid, theta, segi, st, Sn, khi, gbar=gbar)
+    torch.cuda.synchronize()
+    print(f"profile_run done: gradient workload, {theta.shape[0]} triggers, {bins} bins per dispatch; "
+          f"{args.steps} forward then {args.steps} forward+adjoint dispatches")
 
 
 if __name__ == "__main__":

@@ -11,6 +11,9 @@ calibration copy kernel read and write exactly --copy-mib MiB.
 (kernel=output elements per dispatch, comma-separated) and the kernel trace of
 --stats it writes VALU instructions per element and the VALU issue fraction
 (wave64 instructions x 4 cycles / (duration x 2.4 GHz x 1024 SIMDs)).
+--flops: a `rocprofv3 --pmc SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,F64}` run; per
+dispatch, flops = 64 x (add + mul + trans + 2 fma) for each precision, listed in
+dispatch order, per element with --elements.
 """
 from __future__ import annotations
 
@@ -85,6 +88,8 @@ def main():
     ap.add_argument("--sq")
     ap.add_argument("--command-sq", default="")
     ap.add_argument("--elements", default="")
+    ap.add_argument("--flops")
+    ap.add_argument("--command-flops", default="")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     khash = kernel_hash()
@@ -151,7 +156,45 @@ def main():
                 if k in dur and dur[k] > 0:
                     frac = valu * 4.0 / (dur[k] * 1e-9 * 2.4e9 * 1024.0)
                     fh.write(f"avg_duration_us: {dur[k] / 1e3:.2f}\nvalu_issue_fraction: {frac:.3f}\n")
+    if args.flops:
+        rows = list(csv.DictReader(open(find(args.flops, "*counter_collection.csv"))))
+        per = {}
+        for r in rows:
+            key = (short(r["Kernel_Name"]), int(r.get("Dispatch_Id", 0)))
+            per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        elements = dict(kv.split("=") for kv in args.elements.split(",") if kv)
+        by_kernel = {}
+        for (k, d), c in sorted(per.items(), key=lambda x: x[0][1]):
+            def fl(p):
+                return 64.0 * (c.get(f"SQ_INSTS_VALU_ADD_{p}", 0.0) + c.get(f"SQ_INSTS_VALU_MUL_{p}", 0.0) +
+                               c.get(f"SQ_INSTS_VALU_TRANS_{p}", 0.0) + 2.0 * c.get(f"SQ_INSTS_VALU_FMA_{p}", 0.0))
+            by_kernel.setdefault(k, []).append((fl("F32"), fl("F64")))
+        for k, lst in sorted(by_kernel.items()):
+            if k not in elements:
+                continue
+            el = float(elements[k])
+            path = os.path.join(args.out, f"flops_{k}_{args.workload}.txt")
+            with open(path, "w") as fh:
+                fh.write(f"# VALU flops per dispatch of {k}, workload {args.workload}\n")
+                fh.write(f"# command: {args.command_flops}\nkernel_source_hash: {khash}\n")
+                fh.write(f"dispatches: {len(lst)}\nelements_per_dispatch: {el:.0f}\n")
+                for name, vals in (("fp32", [a / el for a, _ in lst]), ("fp64", [b / el for _, b in lst]),
+                                   ("total", [(a + b) / el for a, b in lst])):
+                    fh.write(f"{name}_flops_per_element_mean: {statistics.mean(vals):.2f}\n"
+                             f"{name}_flops_per_element_min: {min(vals):.2f}\n"
+                             f"{name}_flops_per_element_max: {max(vals):.2f}\n")
+                if k in dur_all(args.stats):
+                    d_ns = dur_all(args.stats)[k]
+                    tot = statistics.mean(a + b for a, b in lst)
+                    fh.write(f"avg_duration_us: {d_ns / 1e3:.2f}\nachieved_tflops: {tot / (d_ns * 1e-9) / 1e12:.2f}\n")
     print("written to", args.out)
+
+
+def dur_all(stats_dir):
+    if not stats_dir:
+        return {}
+    return {short(r["Name"]): float(r.get("AverageNs", 0.0))
+            for r in csv.DictReader(open(find(stats_dir, "*kernel_stats.csv")))}
 
 
 if __name__ == "__main__":
