@@ -17,6 +17,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2|3|5]
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import hashlib
 import json
 import math
@@ -37,6 +39,18 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f)
                   for f in ("k_filter.hip", "k_filter_chisq.hip", "filter_tiles.hpp", "mf_device.hpp")]
+
+
+@contextlib.contextmanager
+def quiet_gc():
+    """Timed regions run with a fresh heap and the garbage collector off (as timeit
+    does): a full collection of an interpreter that holds torch takes tens of ms."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def kernel_hash() -> str:
@@ -166,11 +180,12 @@ def run_gpu(args):
         torch.cuda.synchronize()
         lib = L.load()
         lib.mf_timing_enable(stride)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res = mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res = mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         import ctypes as C
         ms, nl, u1, u2 = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
         L.check(lib.mf_timing_read(C.byref(ms), C.byref(nl), C.byref(u1), C.byref(u2)))
@@ -202,11 +217,12 @@ def run_gpu(args):
         torch.cuda.synchronize()
         lib = L.load()
         lib.mf_timing_enable(stride)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res = mf.filter_chisq(grid, bank, st, Sn, P, prec, p_bands=p_bands, workspace=ws)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res = mf.filter_chisq(grid, bank, st, Sn, P, prec, p_bands=p_bands, workspace=ws)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         ms, nl, u1, u2 = (C.c_double * 3)(), (C.c_int64 * 3)(), (C.c_int64 * 3)(), (C.c_int64 * 3)()
         L.check(lib.mf_timing_read_split(ms, nl, u1, u2))
         lib.mf_timing_enable(0)
@@ -232,11 +248,12 @@ def run_gpu(args):
             return r, c
         step()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res, chi = step()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res, chi = step()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         ev = res["seg_events"]
         t, j, rho = ev["t"].cpu().numpy(), ev["j"].cpu().numpy(), ev["rho"].cpu().numpy()
         chi = chi.cpu().numpy()
@@ -257,11 +274,12 @@ def run_gpu(args):
         peaks = torch.empty(2 * bank.n_tmpl, dtype=torch.float64, device=dev)
         mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         del ws
         return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl, "n": g4.n,
                 "plan": mf.filter_plan(g4, prec)}
@@ -285,11 +303,12 @@ def run_gpu(args):
         graph.replay()
         torch.cuda.synchronize()
         same = bool(torch.equal(peaks, eager))
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                graph.replay()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         same = same and bool(torch.equal(peaks, eager))
         del graph
         return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl * n_seg,
@@ -354,10 +373,11 @@ def run_refine(args):
     # warm-up, then the timed refinement
     R.refine(grid, theta0[:64], segi[:64], st, Sn, khi[:64], steps=1)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    theta, F, evals = R.refine(grid, theta0, segi, st, Sn, khi, steps=args.refine_steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with quiet_gc():
+        t0 = time.perf_counter()
+        theta, F, evals = R.refine(grid, theta0, segi, st, Sn, khi, steps=args.refine_steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     # finite-difference check of the adjoint on 64 triggers, at their starting
     # points (after refinement the gradient vanishes and a relative check is void)
     sel = torch.arange(0, n_trig, max(1, n_trig // 64), device=dev)[:64]
@@ -413,7 +433,7 @@ def launches_per_step(m) -> int:
     """Transform launches in one mf_filter call under the plan."""
     u = m["plan"]["units_per_batch"]
     nb = -(-m["units"] // u)
-    return nb + 1 if m["plan"]["fused"] else 2 * nb
+    return nb + 1 if m["plan"]["flags"] & 1 else 2 * nb
 
 
 def roofline(m, workload_name: str, khash: str):
@@ -425,7 +445,7 @@ def roofline(m, workload_name: str, khash: str):
     bytes_per_launch = k["bytes"] / k["launches"]
     ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     prec = "fp64" if m["prec"] == "fp64" else "fp32"
-    fused = bool(m["plan"]["fused"])
+    fused = bool(m["plan"]["flags"] & 1)
     shape = f"{m['plan']['n1']}x{m['plan']['n2']}"
     names = [f"k_step_{prec}_{shape}"] if fused else [f"k_pass1_{prec}_{shape}", f"k_pass2_{prec}_{shape}"]
     rec = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -468,11 +488,11 @@ def chisq_roofline(c, wl, khash: str):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--precision", default="fp32_ph64", choices=["fp32_ph64", "fp32", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--timing-stride", type=int, default=7)  # odd: samples both pass kinds
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-procs", type=int, default=16)

@@ -130,8 +130,11 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
 /*
  * The launch plan mf_filter uses for this grid and precision (after any
  * tuning): plan[0..7] = {N1, N2, columns per pass-1 work-group, rows per
- * pass-2 work-group, pass-1 threads, pass-2 threads, units per batch,
- * 1 if pass 1 of batch b and pass 2 of batch b-1 share a launch}.
+ * pass-2 work-group, pass-1 threads, pass-2 threads, units per batch, flags}.
+ * flags bit 0: pass 1 of batch b and pass 2 of batch b-1 share a launch;
+ * bit 1: the pass-2 stages exchange real and imaginary parts one after the
+ * other through half the LDS (more work-groups per CU).  The two bits
+ * exclude each other.
  */
 mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 

@@ -145,7 +145,7 @@ def filter_plan(grid: Grid, precision="fp32_ph64") -> dict:
     arr = (C.c_int32 * 8)()
     g = grid.c()
     L.check(_clib.mf_filter_plan(C.byref(g), _prec(precision), arr))
-    keys = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "fused")
+    keys = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "flags")
     return dict(zip(keys, [int(x) for x in arr]))
 
 
@@ -154,7 +154,7 @@ def filter_chisq_plan(grid: Grid, precision="fp32_ph64") -> dict:
     arr = (C.c_int32 * 8)()
     g = grid.c()
     L.check(_clib.mf_filter_chisq_plan(C.byref(g), _prec(precision), arr))
-    keys = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "fused")
+    keys = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "flags")
     return dict(zip(keys, [int(x) for x in arr]))
 
 

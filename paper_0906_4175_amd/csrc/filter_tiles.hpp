@@ -65,6 +65,7 @@ __device__ __forceinline__ void powers(cx<T> w, cx<T>* p) {
 }
 
 __host__ __device__ constexpr int pad16(int k) { return k + (k >> 4); }
+__host__ __device__ constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
 
 // Event keys: larger key = larger |z|^2, then lower index.  FP32 keeps the
 // float bits and the sample index; FP64 keeps |z|^2 to 36 mantissa bits and
@@ -154,6 +155,17 @@ struct Pass1 {
                     const int j = bf / C;
                     if constexpr (s == 0) {
                         const int64_t k2 = k2_0 + c;
+                        // every weight load of the butterfly is issued before the
+                        // first rotor (bins outside [k_lo, k_hi] load bin 0 and are
+                        // discarded), so a wave waits for memory once
+                        cx<T> wk[RAW ? 1 : R / 2];
+                        if constexpr (!RAW) {
+#pragma unroll
+                            for (int r = 0; r < R / 2; ++r) {
+                                const int64_t k = (j + r * (N1 / R)) * (int64_t)N2 + k2;
+                                wk[r] = w[(k >= klo && k <= khi) ? k : 0];
+                            }
+                        }
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int64_t k1 = j + r * (N1 / R);
@@ -170,7 +182,7 @@ struct Pass1 {
                                         } else {
                                             rotor = spa_rotor_ph32(coef, (float)k);
                                         }
-                                        v[i][r] = cmul(rotor, w[k]);
+                                        v[i][r] = cmul(rotor, wk[r]);
                                     }
                                     if constexpr (MODE == P1_BAND) {
                                         qout[k] = v[i][r];
@@ -234,7 +246,7 @@ struct Pass1 {
 // twiddle pass is needed and the result is exact (not only up to a phase).
 // The last stage squares |z| and reduces (max |z|^2, lowest index, count).
 // ---------------------------------------------------------------------------
-template <typename T, bool RAW, int N1, int N2, int B, int NT, int MAXR = 16>
+template <typename T, bool RAW, int N1, int N2, int B, int NT, int MAXR = 16, bool XSPLIT = false>
 struct Pass2 {
     static constexpr int64_t N = (int64_t)N1 * N2;
     static constexpr int NS = num_stages(N2, MAXR);
@@ -243,8 +255,21 @@ struct Pass2 {
     static constexpr int TW = tw_total(N2, MAXR);
     static constexpr bool F64 = std::is_same<T, double>::value;
     static constexpr int R0 = radix_at(N2, 0, MAXR);
-    static constexpr size_t SMEM =
-        (size_t)(B * PN2 + TW + B * NS + B * R0) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
+    // XSPLIT: exchange the real parts, then the imaginary parts, through a
+    // buffer of B * PN2 scalars (half the LDS, so more work-groups per CU,
+    // for two more barriers per exchange); needs the same radix at every stage.
+    static constexpr bool SPLIT = XSPLIT;
+    static_assert(!XSPLIT || (N2 == ipow_c(MAXR, NS) && NS > 1), "split exchange needs one radix at every stage");
+    // FP32 peak search over the full series when every thread holds exactly
+    // one last-stage butterfly: each thread keeps its largest |z|^2 bits, the
+    // work-group takes the maximum, and only threads that hold it look for
+    // its lowest index (instead of every thread building a 64-bit key).
+    static constexpr int RL = radix_at(N2, NS - 1, MAXR);
+    static constexpr int SPAN_L = span_before(N2, NS - 1, MAXR);
+    static constexpr bool DEFER = !F64 && !RAW && B * N2 / RL == NT;
+    static constexpr size_t BUF_BYTES = (size_t)B * PN2 * (SPLIT ? sizeof(T) : sizeof(cx<T>));
+    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + B * NS + B * R0) * sizeof(cx<T>) +
+                                   (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
 
     // LDS element offset of padded index x + r * step when x's padding is known
@@ -259,7 +284,8 @@ struct Pass2 {
 
     __device__ static void run(const FilterArgs& a, char* smem, int rb, int64_t ul) {
         cx<T>* buf = (cx<T>*)smem;
-        cx<T>* tw = buf + B * PN2;
+        T* fbuf = (T*)smem;  // SPLIT: [B][PN2] scalars
+        cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);
         cx<T>* trow = tw + TW;  // [B][NS]: t^{weight_s} per row
         cx<T>* pow0 = trow + B * NS;  // [B][R0]: (t^{weight_0})^r, the stage-0 factors of each row
         unsigned long long* red_key = (unsigned long long*)(pow0 + B * R0);
@@ -305,7 +331,16 @@ struct Pass2 {
         double best_zz = -1.0;
         int best_j = 0x7fffffff;
         unsigned int cnt = 0u;
+        // DEFER: the thread's last-stage |z|^2, their maximum bits and the
+        // sample index of output r = 0 (output r is at djg + r N1 SPAN_L)
+        [[maybe_unused]] T dzz[DEFER ? RL : 1];
+        [[maybe_unused]] unsigned int dmax = 0u;
+        [[maybe_unused]] int djg = 0;
         __syncthreads();
+
+        // SPLIT: the next stage's inputs, read during the exchange
+        constexpr int CBPT = (B * N2 / R0 + NT - 1) / NT;
+        cx<T> carry[SPLIT ? CBPT : 1][SPLIT ? R0 : 1];
 
         static_for<0, NS>([&](auto S_) {
             constexpr int s = decltype(S_)::value;
@@ -330,9 +365,14 @@ struct Pass2 {
                         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pow0[b * R0 + r]);
                     } else {
                         const int k = j % NSPAN;
-                        const cx<T>* src = buf + b * PN2;
+                        if constexpr (SPLIT) {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
+                            for (int r = 0; r < R; ++r) v[i][r] = carry[i][r];
+                        } else {
+                            const cx<T>* src = buf + b * PN2;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
+                        }
                         cx<T> p[R];
                         powers<R>(cmul(tw[tw_offset(N2, s, MAXR) + k], trow[b * NS + s]), p);
 #pragma unroll
@@ -371,9 +411,21 @@ struct Pass2 {
                                 }
                             }
                             if (full_window) {
-                                if (count_on) {
+                                // FP32: integer max of the non-negative float bits (NaN
+                                // bits exceed +inf, so a NaN propagates)
+                                unsigned int mb = 0u;
+                                if constexpr (!F64) {
+                                    mb = __float_as_uint(zz[0]);
 #pragma unroll
-                                    for (int r = 0; r < R; ++r) cnt += (zz[r] >= thr2) ? 1u : 0u;
+                                    for (int r = 1; r < R; ++r) mb = max(mb, __float_as_uint(zz[r]));
+                                }
+                                if (count_on) {
+                                    // FP32: almost no butterfly reaches the threshold, so
+                                    // its largest |z|^2 is tested first
+                                    if (F64 || mb >= __float_as_uint((float)thr2)) {
+#pragma unroll
+                                        for (int r = 0; r < R; ++r) cnt += (zz[r] >= thr2) ? 1u : 0u;
+                                    }
                                 }
                                 if (a.ev_keys != nullptr) {
                                     // events: rare samples at or above the threshold update their window
@@ -398,12 +450,13 @@ struct Pass2 {
                                             best_j = jg;
                                         }
                                     }
-                                } else {
-                                    // integer max of the non-negative float bits (NaN bits exceed +inf,
-                                    // so a NaN propagates), then the lowest r that attains it
-                                    unsigned int mb = __float_as_uint(zz[0]);
+                                } else if constexpr (DEFER) {
+                                    dmax = mb;
+                                    djg = j1 + N1 * j;
 #pragma unroll
-                                    for (int r = 1; r < R; ++r) mb = max(mb, __float_as_uint(zz[r]));
+                                    for (int r = 0; r < R; ++r) dzz[r] = zz[r];
+                                } else {
+                                    // the lowest r that attains the maximum
                                     int rmin = R - 1;
 #pragma unroll
                                     for (int r = R - 2; r >= 0; --r) rmin = __float_as_uint(zz[r]) == mb ? r : rmin;
@@ -435,6 +488,40 @@ struct Pass2 {
                         }
                     }
                 }
+            } else if constexpr (SPLIT) {
+                // same positions as below, one component at a time; the next
+                // stage has the same radix, so the same (j, b) per thread
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i) {
+                        const int bf = tid + i * NT;
+                        if (NBF % NT == 0 || bf < NBF) {
+                            const int j = bf % PER_ROW;
+                            const int b = bf / PER_ROW;
+                            const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
+                            T* dst = fbuf + b * PN2;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) dst[off<NSPAN>(idxD, r)] = part ? v[i][r].y : v[i][r].x;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i) {
+                        const int bf = tid + i * NT;
+                        if (NBF % NT == 0 || bf < NBF) {
+                            const int j = bf % PER_ROW;
+                            const int b = bf / PER_ROW;
+                            const T* src = fbuf + b * PN2;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                if (part) carry[i][r].y = src[off<PER_ROW>(j, r)];
+                                else carry[i][r].x = src[off<PER_ROW>(j, r)];
+                            }
+                        }
+                    }
+                }
             } else {
                 __syncthreads();
 #pragma unroll
@@ -459,6 +546,45 @@ struct Pass2 {
             }
         });
 
+        if constexpr (DEFER) {
+            if (full_window) {
+                const int lane = tid & 63;
+                const int wave = tid >> 6;
+                unsigned int m = dmax;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    cnt += __shfl_xor(cnt, o, 64);
+                    m = max(m, (unsigned int)__shfl_xor(m, o, 64));
+                }
+                unsigned int* red_max = (unsigned int*)red_j;
+                if (lane == 0) {
+                    red_cnt[wave] = cnt;
+                    red_max[wave] = m;
+                }
+                if (tid == 0) red_key[0] = 0ull;
+                __syncthreads();
+                unsigned int bmax = red_max[0];
+#pragma unroll
+                for (int wv = 1; wv < NWAVE; ++wv) bmax = max(bmax, red_max[wv]);
+                if (dmax == bmax) {
+                    // rare: the lowest r of this thread that attains the maximum
+                    int rmin = RL - 1;
+#pragma unroll
+                    for (int r = RL - 2; r >= 0; --r) rmin = __float_as_uint(dzz[r]) == bmax ? r : rmin;
+                    const unsigned int jg = (unsigned int)(djg + N1 * rmin * SPAN_L);
+                    atomicMax(red_key, ((unsigned long long)bmax << 32) | (unsigned long long)(0xffffffffu - jg));
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    unsigned int total = 0u;
+#pragma unroll
+                    for (int wv = 0; wv < NWAVE; ++wv) total += red_cnt[wv];
+                    atomicMax(a.keys + u, red_key[0]);
+                    if (total) atomicAdd(a.counts + u, total);
+                }
+                return;
+            }
+        }
         if constexpr (!RAW) {
             // work-group reduction: wave shuffles, then one LDS slot per wave
             const int lane = tid & 63;

@@ -34,9 +34,9 @@ __global__ void __launch_bounds__(NT) k_pass1(FilterArgs a) {
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, bool RAW, int N1, int N2, int B, int NT, int R2>
+template <typename T, bool RAW, int N1, int N2, int B, int NT, int R2, bool XS>
 __global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
-    using P = Pass2<T, RAW, N1, N2, B, NT, R2>;
+    using P = Pass2<T, RAW, N1, N2, B, NT, R2, XS>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
@@ -132,27 +132,30 @@ size_t cx_bytes(mf_precision prec) { return prec == MF_FP64 ? 16 : 8; }
 
 static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024 : x); }
 
-// Every (precision, N1, N2, C, B, R2) instantiated (R2: largest radix of the
-// pass-2 stages, 16 or 8; it sets the pass-2 threads B N2 / R2).  The first
-// entry for each N and precision is its default plan.
-#define MF_SHAPES(X)                                                                                      \
-    X(float, 32, 32, 16, 32, 16) X(float, 32, 64, 16, 32, 16) X(float, 64, 64, 16, 64, 16) X(float, 64, 128, 16, 32, 16)  \
-    X(float, 128, 128, 16, 32, 16) X(float, 128, 256, 16, 16, 16) X(float, 256, 256, 16, 16, 16)                       \
-    X(float, 256, 512, 16, 8, 16) X(float, 512, 512, 16, 8, 16) X(float, 512, 1024, 16, 4, 16)                          \
-    X(float, 256, 4096, 16, 1, 16) X(float, 1024, 2048, 16, 2, 16) X(float, 1024, 4096, 8, 1, 16)                       \
-    X(float, 1024, 1024, 8, 4, 16) X(float, 1024, 1024, 16, 8, 16) X(float, 1024, 1024, 16, 4, 16)                      \
-    X(float, 512, 2048, 16, 2, 16) X(float, 2048, 512, 8, 8, 16) X(float, 2048, 2048, 8, 2, 16) X(float, 1024, 4096, 16, 1, 16) \
-    X(float, 512, 8192, 16, 1, 16) X(float, 256, 4096, 16, 1, 8) X(float, 1024, 4096, 8, 1, 8)                                                                              \
-    X(double, 32, 32, 8, 32, 16) X(double, 32, 64, 8, 32, 16) X(double, 64, 64, 8, 64, 16) X(double, 64, 128, 8, 32, 16)   \
-    X(double, 128, 128, 8, 32, 16) X(double, 128, 256, 8, 16, 16) X(double, 256, 256, 8, 16, 16)                        \
-    X(double, 256, 512, 8, 8, 16) X(double, 512, 512, 8, 8, 16) X(double, 512, 1024, 8, 4, 16)                          \
-    X(double, 512, 2048, 8, 2, 16) X(double, 1024, 2048, 4, 2, 16) X(double, 2048, 2048, 2, 2, 16)                      \
-    X(double, 1024, 1024, 8, 4, 16) X(double, 1024, 1024, 4, 4, 16) X(double, 1024, 1024, 4, 2, 16)            \
-    X(double, 512, 2048, 8, 2, 8)
+// Every (precision, N1, N2, C, B, R2, XS) instantiated (R2: largest radix of
+// the pass-2 stages, 16 or 8; it sets the pass-2 threads B N2 / R2.  XS: the
+// pass-2 stages exchange real and imaginary parts separately, in half the
+// LDS).  The first entry for each N and precision is its default plan.
+#define MF_SHAPES(X)                                                                                              \
+    X(float, 32, 32, 16, 32, 16, 0) X(float, 32, 64, 16, 32, 16, 0) X(float, 64, 64, 16, 64, 16, 0)                 \
+    X(float, 64, 128, 16, 32, 16, 0) X(float, 128, 128, 16, 32, 16, 0) X(float, 128, 256, 16, 16, 16, 0)            \
+    X(float, 256, 256, 16, 16, 16, 0) X(float, 256, 512, 16, 8, 16, 0) X(float, 512, 512, 16, 8, 16, 0)             \
+    X(float, 512, 1024, 16, 4, 16, 0) X(float, 256, 4096, 16, 1, 16, 1) X(float, 256, 4096, 16, 1, 16, 0)           \
+    X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 8, 1, 16, 0) X(float, 1024, 4096, 8, 1, 16, 1)          \
+    X(float, 1024, 1024, 8, 4, 16, 0) X(float, 1024, 1024, 16, 8, 16, 0) X(float, 1024, 1024, 16, 4, 16, 0)         \
+    X(float, 512, 2048, 16, 2, 16, 0) X(float, 2048, 512, 8, 8, 16, 0) X(float, 2048, 2048, 8, 2, 16, 0)            \
+    X(float, 1024, 4096, 16, 1, 16, 0) X(float, 512, 8192, 16, 1, 16, 0) X(float, 256, 4096, 16, 1, 8, 0)           \
+    X(float, 1024, 4096, 8, 1, 8, 0)                                                                              \
+    X(double, 32, 32, 8, 32, 16, 0) X(double, 32, 64, 8, 32, 16, 0) X(double, 64, 64, 8, 64, 16, 0)                 \
+    X(double, 64, 128, 8, 32, 16, 0) X(double, 128, 128, 8, 32, 16, 0) X(double, 128, 256, 8, 16, 16, 0)            \
+    X(double, 256, 256, 8, 16, 16, 0) X(double, 256, 512, 8, 8, 16, 0) X(double, 512, 512, 8, 8, 16, 0)             \
+    X(double, 512, 1024, 8, 4, 16, 0) X(double, 512, 2048, 8, 2, 16, 0) X(double, 1024, 2048, 4, 2, 16, 0)          \
+    X(double, 2048, 2048, 2, 2, 16, 0) X(double, 1024, 1024, 8, 4, 16, 0) X(double, 1024, 1024, 4, 4, 16, 0)        \
+    X(double, 1024, 1024, 4, 2, 16, 0) X(double, 512, 2048, 8, 2, 8, 0)
 
 static bool want(mf_precision prec, bool f64) { return (prec == MF_FP64) == f64; }
 
-static void fill(Plan& p, int n1, int n2, int c1, int b2, int r2) {
+static void fill(Plan& p, int n1, int n2, int c1, int b2, int r2, int xs) {
     p.n1 = n1;
     p.n2 = n2;
     p.c1 = c1;
@@ -161,16 +164,17 @@ static void fill(Plan& p, int n1, int n2, int c1, int b2, int r2) {
     p.nt2 = clamp_threads(b2 * n2 / r2);
     p.log2n = ilog2((long long)n1 * n2);
     p.fused = p.nt1 == p.nt2;
+    p.split = xs != 0;
 }
 
 int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
     int n = 0;
-#define MF_CAND(T, N1, N2, C, B, R2)                                                                    \
+#define MF_CAND(T, N1, N2, C, B, R2, XS)                                                                \
     if (want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n) {            \
         Plan q{};                                                                                      \
-        fill(q, N1, N2, C, B, R2);                                                                     \
+        fill(q, N1, N2, C, B, R2, XS);                                                                 \
         q.units = 0;                                                                                   \
-        for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 ? 2 : 1); ++f) {                               \
+        for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 && !XS ? 2 : 1); ++f) {                        \
             q.fused = f == 1;                                                                          \
             if (out && n < cap) out[n] = q;                                                            \
             ++n;                                                                                       \
@@ -182,9 +186,9 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
 }
 
 bool plan_supported(const Plan& q, mf_precision prec) {
-#define MF_MATCH(T, N1, N2, C, B, R2)                                                                      \
+#define MF_MATCH(T, N1, N2, C, B, R2, XS)                                                                  \
     if (want(prec, std::is_same<T, double>::value) && q.n1 == N1 && q.n2 == N2 && q.c1 == C && q.b2 == B && \
-        q.nt2 == clamp_threads(B * N2 / R2))                                                                 \
+        q.nt2 == clamp_threads(B * N2 / R2) && q.split == (XS != 0) && !(q.fused && XS))                     \
         return true;
     MF_SHAPES(MF_MATCH)
 #undef MF_MATCH
@@ -195,9 +199,9 @@ Plan default_plan(int log2n, mf_precision prec) {
     Plan p{};
     p.log2n = -1;
     bool found = false;
-#define MF_FIRST(T, N1, N2, C, B, R2)                                                                             \
+#define MF_FIRST(T, N1, N2, C, B, R2, XS)                                                                         \
     if (!found && want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n) {           \
-        fill(p, N1, N2, C, B, R2);                                                                                \
+        fill(p, N1, N2, C, B, R2, XS);                                                                            \
         found = true;                                                                                             \
     }
     MF_SHAPES(MF_FIRST)
@@ -247,17 +251,17 @@ static hipError_t run_pass1(const FilterArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, bool RAW, int N1, int N2, int B, int R2>
+template <typename T, bool RAW, int N1, int N2, int B, int R2, bool XS>
 static hipError_t run_pass2(const FilterArgs& a, hipStream_t s) {
     static_assert(N1 % B == 0 && B <= N1, "pass-2 rows per work-group must tile N1");
     constexpr int NT = clamp_threads(B * N2 / R2);
     dim3 grid(N1 / B, (unsigned)a.units);
-    hipLaunchKernelGGL((k_pass2<T, RAW, N1, N2, B, NT, R2>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_pass2<T, RAW, N1, N2, B, NT, R2, XS>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s) {
-#define MF_P1(T, N1, N2, C, B, R2)                                                                              \
+#define MF_P1(T, N1, N2, C, B, R2, XS)                                                                          \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {    \
         if (raw) return run_pass1<T, 0, P1_RAW, N1, N2, C>(a, s);                                              \
         if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
@@ -270,10 +274,11 @@ hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const Filter
 }
 
 hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s) {
-#define MF_P2(T, N1, N2, C, B, R2)                                                                           \
+#define MF_P2(T, N1, N2, C, B, R2, XS)                                                                       \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B && \
-        p.nt2 == clamp_threads(B * N2 / R2))                                                                 \
-        return raw ? run_pass2<T, true, N1, N2, B, R2>(a, s) : run_pass2<T, false, N1, N2, B, R2>(a, s);
+        p.nt2 == clamp_threads(B * N2 / R2) && p.split == (XS != 0))                                         \
+        return raw ? run_pass2<T, true, N1, N2, B, R2, XS != 0>(a, s)                                        \
+                   : run_pass2<T, false, N1, N2, B, R2, XS != 0>(a, s);
     MF_SHAPES(MF_P2)
 #undef MF_P2
     return hipErrorInvalidValue;
@@ -293,9 +298,9 @@ static hipError_t run_step(const FilterArgs& a1, const FilterArgs& a2, hipStream
 }
 
 hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
-#define MF_ST(T, N1, N2, C, B, R2)                                                                             \
+#define MF_ST(T, N1, N2, C, B, R2, XS)                                                                         \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B &&   \
-        R2 == 16) {                                                                                           \
+        R2 == 16 && !XS) {                                                                                    \
         if (std::is_same<T, float>::value && prec == MF_FP32) return run_step<float, 1, N1, N2, C, B>(a1, a2, s); \
         return run_step<T, 0, N1, N2, C, B>(a1, a2, s);                                                       \
     }

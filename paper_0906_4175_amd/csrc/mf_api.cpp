@@ -162,8 +162,8 @@ Plan select_plan(int log2n, mf_precision prec) {
     }
     if (const char* e = getenv("MF_PLAN")) {
         Plan q = p;
-        int n1 = 0, n2 = 0, c1 = 0, b2 = 0, r2 = 16;
-        const int got = sscanf(e, "%d,%d,%d,%d,%d", &n1, &n2, &c1, &b2, &r2);
+        int n1 = 0, n2 = 0, c1 = 0, b2 = 0, r2 = 16, xs = 0;
+        const int got = sscanf(e, "%d,%d,%d,%d,%d,%d", &n1, &n2, &c1, &b2, &r2, &xs);
         if (got >= 4 && (int64_t)n1 * n2 == (int64_t(1) << log2n) && (r2 == 8 || r2 == 16)) {
             q.n1 = n1;
             q.n2 = n2;
@@ -172,13 +172,14 @@ Plan select_plan(int log2n, mf_precision prec) {
             q.nt1 = c1 * n1 / 16 < 64 ? 64 : (c1 * n1 / 16 > 1024 ? 1024 : c1 * n1 / 16);
             q.nt2 = b2 * n2 / r2 < 64 ? 64 : (b2 * n2 / r2 > 1024 ? 1024 : b2 * n2 / r2);
             q.fused = false;
+            q.split = xs != 0;
             if (plan_supported(q, prec)) p = q;
         }
     }
     if (const char* e = getenv("MF_FUSED")) {
         const int b16 = p.b2 * p.n2 / 16;
         const int nt16 = b16 < 64 ? 64 : (b16 > 1024 ? 1024 : b16);
-        p.fused = e[0] == '1' && p.nt1 == p.nt2 && p.nt2 == nt16;
+        p.fused = e[0] == '1' && p.nt1 == p.nt2 && p.nt2 == nt16 && !p.split;
     }
     if (const char* e = getenv("MF_UNITS")) {
         const long v = strtol(e, nullptr, 10);
@@ -214,7 +215,7 @@ mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]
     if (st != MF_OK) return st;
     if (!valid_prec(prec) || !plan) return fail(MF_E_ARG, "bad precision or null plan");
     const mf::Plan p = mf::select_plan(l, prec);
-    const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, p.fused ? 1 : 0};
+    const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, (p.fused ? 1 : 0) | (p.split ? 2 : 0)};
     for (int i = 0; i < 8; ++i) plan[i] = v[i];
     return ok();
 }
@@ -230,7 +231,7 @@ int32_t mf_plan_candidates(const mf_grid* grid, mf_precision prec, int32_t* plan
     const int n = mf::plan_candidates(l, prec, v.data(), cap);
     for (int i = 0; i < n && i < cap; ++i) {
         const mf::Plan& p = v[(size_t)i];
-        const int32_t row[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, 0, p.fused ? 1 : 0};
+        const int32_t row[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, 0, (p.fused ? 1 : 0) | (p.split ? 2 : 0)};
         for (int k = 0; k < 8; ++k) plans[8 * i + k] = row[k];
     }
     ok();
@@ -258,10 +259,13 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     const int nt16 = clampt((long long)q.b2 * q.n2 / 16), nt8 = clampt((long long)q.b2 * q.n2 / 8);
     q.nt2 = plan[5] == nt8 ? nt8 : nt16;
     q.units = plan[6];
-    q.fused = plan[7] != 0;
+    if (plan[7] & ~3) return fail(MF_E_ARG, "plan flags %d: only bits 0 (pipelined step) and 1 (split exchange)", plan[7]);
+    q.fused = (plan[7] & 1) != 0;
+    q.split = (plan[7] & 2) != 0;
     if ((int64_t)q.n1 * q.n2 != grid->n || !mf::plan_supported(q, prec))
-        return fail(MF_E_UNSUPPORTED, "plan %dx%d c=%d b=%d (pass-2 threads %d) is not built for this N/precision",
-                    q.n1, q.n2, q.c1, q.b2, q.nt2);
+        return fail(MF_E_UNSUPPORTED,
+                    "plan %dx%d c=%d b=%d (pass-2 threads %d, flags %d) is not built for this N/precision", q.n1, q.n2,
+                    q.c1, q.b2, q.nt2, plan[7]);
     if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
     if (q.fused && (q.nt1 != q.nt2 || q.nt2 != nt16))
         return fail(MF_E_UNSUPPORTED, "pipelined step needs equal work-group sizes and radix-16 row stages");

@@ -26,14 +26,16 @@ struct Plan {
     int nt2;         // threads per pass-2 work-group
     int units;       // (template, segment) units per batch
     bool fused;      // pipelined step kernel (pass 1 of batch b with pass 2 of batch b-1)
+    bool split;      // pass-2 stages exchange real and imaginary parts separately
 };
 
 Plan default_plan(int log2n, mf_precision prec);
 bool plan_supported(const Plan& p, mf_precision prec);
 // instantiated shapes for this N and precision (units = 0); returns the count
 int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap);
-// default plan, overridden by MF_PLAN="n1,n2,c1,b2[,r2]" (r2: largest pass-2
-// radix, 16 or 8) and MF_UNITS="units" when set
+// default plan, overridden by MF_PLAN="n1,n2,c1,b2[,r2[,xs]]" (r2: largest
+// pass-2 radix, 16 or 8; xs: 1 for the split pass-2 exchange) and
+// MF_UNITS="units" when set
 Plan select_plan(int log2n, mf_precision prec);
 
 size_t cx_bytes(mf_precision prec);

@@ -21,7 +21,7 @@ import warnings
 
 from . import _lib as L
 
-PLAN_KEYS = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "fused")
+PLAN_KEYS = ("n1", "n2", "cols_per_wg", "rows_per_wg", "threads_pass1", "threads_pass2", "units_per_batch", "flags")
 
 
 def _prec_class(prec: int) -> str:

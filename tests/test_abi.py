@@ -153,6 +153,24 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert lib.mf_set_plan(C.byref(g), 1, None) == 0
     assert lib.mf_filter_plan(C.byref(g), 1, out) == 0
     assert list(out)[:4] == [256, 4096, 16, 1]
+    # flags: bit 0 pipelined step, bit 1 split pass-2 exchange (the 2^20 FP32 default)
+    assert out[7] == 2
+    flags = {(tuple(buf[8 * i: 8 * i + 6]), buf[8 * i + 7]) for i in range(n)}
+    assert ((256, 4096, 16, 1, 256, 256), 2) in flags and ((256, 4096, 16, 1, 256, 256), 0) in flags
+    assert ((256, 4096, 16, 1, 256, 256), 3) not in flags
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 4)  # unknown flag bit
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -1
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 3)  # pipelined step with the split exchange
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
+    bad = (C.c_int32 * 8)(1024, 1024, 8, 4, 512, 256, 16, 2)  # split exchange not built for this shape
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
+    good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 0)
+    assert lib.mf_set_plan(C.byref(g), 1, good) == 0
+    assert lib.mf_filter_plan(C.byref(g), 1, out) == 0 and out[7] == 0
+    assert lib.mf_set_plan(C.byref(g), 1, None) == 0
+    g22 = _grid(n=1 << 22)
+    assert lib.mf_filter_plan(C.byref(g22), 1, out) == 0
+    assert list(out)[:4] == [1024, 4096, 8, 1] and out[7] == 0
 
 
 def test_tune_cache_corrupt_and_foreign(tmp_path):
@@ -169,7 +187,7 @@ def test_tune_cache_corrupt_and_foreign(tmp_path):
     assert tune.load_cache(str(p), arch="gfx950") == 0
     # a valid entry for this architecture is installed, a bad one is skipped
     plan = dict(n1=1024, n2=1024, cols_per_wg=8, rows_per_wg=4, threads_pass1=512, threads_pass2=256,
-                units_per_batch=32, fused=0)
+                units_per_batch=32, flags=0)
     tune.save_cache(str(p), "gfx950", 1 << 20, 1, plan, 1.0)
     tune.save_cache(str(p), "gfx950", 1 << 16, 1, dict(plan, n1=7), 1.0)
     with warnings.catch_warnings(record=True):
