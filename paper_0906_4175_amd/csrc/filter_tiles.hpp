@@ -101,11 +101,18 @@ struct Pass1 {
     static constexpr int64_t N = (int64_t)N1 * N2;
     static constexpr int NS = num_stages(N1);
     static constexpr int TW = tw_total(N1);
-    static constexpr size_t SMEM = (size_t)(N1 * C + TW) * sizeof(cx<T>);
+    // FP32: stage 1 reads its factors w^(k r), k < 16, r < R1, from a full
+    // table (the same for every column) instead of forming powers per
+    // butterfly (FP64 keeps the powers: its roots cost more than the products)
+    static constexpr bool USE_T1 = NS >= 2 && sizeof(T) == 4;
+    static constexpr int R1 = NS >= 2 ? radix_at(N1, 1) : 1;
+    static constexpr int T1 = USE_T1 ? 16 * R1 : 0;
+    static constexpr size_t SMEM = (size_t)(N1 * C + TW + T1) * sizeof(cx<T>);
 
     __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
         cx<T>* buf = (cx<T>*)smem;
         cx<T>* tw = buf + N1 * C;
+        cx<T>* t1 = tw + TW;  // [k][r]
         const int tid = threadIdx.x;
         const int k2_0 = tile * C;
         const int64_t u = a.unit0 + ul;
@@ -197,14 +204,28 @@ struct Pass1 {
 #pragma unroll
                         for (int r = 0; r < R; ++r) v[i][r] = src[r * (N1 / R) * C];
                         cx<T> p[R];
-                        powers<R>(tw[tw_offset(N1, s) + k], p);
+                        if constexpr (s == 1 && USE_T1) {
+                            static_assert(NSPAN == 16 && R == R1, "stage-1 table shape");
+#pragma unroll
+                            for (int r = 1; r < R; ++r) p[r] = t1[k * R + r];
+                        } else {
+                            powers<R>(tw[tw_offset(N1, s) + k], p);
+                        }
 #pragma unroll
                         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
                     }
                     IDft<R, T>::run(v[i]);
                 }
             }
-            if constexpr (s == 0) fill_stage_twiddles<T, N1>(tw, tid, NT);
+            if constexpr (s == 0) {
+                fill_stage_twiddles<T, N1>(tw, tid, NT);
+                // each factor from its exactly reduced argument (k r mod 16 R1) / (16 R1)
+                constexpr T INV_M1 = (T)1 / (T)(16 * R1);  // a power of two: exact
+                for (int q = tid; q < T1; q += NT) {
+                    const int k = q / R1, r = q % R1;
+                    t1[q] = root_of_unity((T)((k * r) & (16 * R1 - 1)) * INV_M1);
+                }
+            }
             if constexpr (s == NS - 1) {
 #pragma unroll
                 for (int i = 0; i < BPT; ++i) {
