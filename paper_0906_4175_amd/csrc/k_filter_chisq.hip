@@ -97,8 +97,21 @@ struct Pass2Band {
     static constexpr int NBFL = B * N2 / RL;
     static constexpr int BPTL = (NBFL + NT - 1) / NT;
     static constexpr bool F64 = std::is_same<T, double>::value;
+    // The stage factors do not depend on the band, so stages 0 and 1 read
+    // theirs from per-row tables filled once: [B][R0] and [B][R1][span_1]
+    // (r-major, so lanes with consecutive k read consecutive entries).
+    // (Shapes with many rows per work-group keep the powers where a table
+    // would crowd LDS.)
+    static constexpr int R0 = radix_at(N2, 0, MAXR);
+    static constexpr int R1 = NS >= 2 ? radix_at(N2, 1, MAXR) : 1;
+    static constexpr int SP1 = NS >= 2 ? span_before(N2, 1, MAXR) : 0;
+    static constexpr bool USE_F0 = B * R0 * sizeof(cx<T>) <= 4096;
+    static constexpr bool USE_F1 = NS >= 2 && B * R1 * SP1 * sizeof(cx<T>) <= 8192;
+    static constexpr int NF0 = USE_F0 ? B * R0 : 0;
+    static constexpr int NF1 = USE_F1 ? B * R1 * SP1 : 0;
+    static constexpr int TAB = NF0 + NF1;
     static constexpr size_t SMEM =
-        (size_t)(B * PN2 + TW + B * NS + B * HALF) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
+        (size_t)(B * PN2 + TW + B * NS + B * HALF + TAB) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
 
     template <int STEP>
@@ -115,7 +128,9 @@ struct Pass2Band {
         cx<T>* tw = buf + B * PN2;
         cx<T>* trow = tw + TW;   // [B][NS]: t^{weight_s} per row
         cx<T>* om = trow + B * NS;  // [B][N1/2]: e^{2 pi i j1 k1 / N1}
-        double* red_zz = (double*)(om + B * HALF);
+        cx<T>* f0 = om + B * HALF;  // [B][R0]: stage-0 factors
+        cx<T>* f1 = f0 + NF0;       // [B][R1][SP1]: stage-1 factors
+        double* red_zz = (double*)(f1 + NF1);
         double* red_chi = red_zz + NWAVE;
         int* red_j = (int*)(red_chi + NWAVE);
         unsigned int* red_cnt = (unsigned int*)(red_j + NWAVE);
@@ -140,6 +155,18 @@ struct Pass2Band {
             om[m] = root_of_unity((T)jk / (T)N1);
         }
         fill_stage_twiddles<T, N2, MAXR>(tw, tid, NT);
+        // stage s multiplies input r by e^{2 pi i r w_s (k N1 + j1) / N}, w_s = N2 / (span_s R_s):
+        // each entry from its exactly reduced integer argument
+        for (int q = tid; q < NF0; q += NT) {
+            const int64_t j1 = rb * B + q / R0, r = q % R0;
+            const int64_t m = ((int64_t)digit_weight(N2, 0, MAXR) * j1 % N) * r % N;
+            f0[q] = root_of_unity((T)m / (T)N);
+        }
+        for (int q = tid; q < NF1; q += NT) {
+            const int64_t j1 = rb * B + q / (R1 * SP1), r = (q / SP1) % R1, k = q % SP1;
+            const int64_t m = ((int64_t)digit_weight(N2, 1, MAXR) * ((int64_t)k * N1 + j1) % N) * r % N;
+            f1[q] = root_of_unity((T)m / (T)N);
+        }
 
         const mf_bank_entry e = a.bank[t];
         const double sigma = e.sigma;
@@ -182,7 +209,7 @@ struct Pass2Band {
                     if (NBF % NT == 0 || bf < NBF) {
                         const int j = bf % PER_ROW;
                         const int b = bf / PER_ROW;
-                        cx<T> base = trow[b * NS + s];
+                        [[maybe_unused]] cx<T> base = trow[b * NS + s];
                         if constexpr (s == 0) {
                             if (from_inter) {
                                 const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
@@ -206,10 +233,19 @@ struct Pass2Band {
                             const cx<T>* src = buf + b * PN2;
 #pragma unroll
                             for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
-                            base = cmul(tw[tw_offset(N2, s, MAXR) + k], base);
+                            if constexpr (s >= 2 || !USE_F1) base = cmul(tw[tw_offset(N2, s, MAXR) + k], base);
                         }
                         cx<T> pw[R];
-                        powers<R>(base, pw);
+                        if constexpr (s == 0 && USE_F0) {
+#pragma unroll
+                            for (int r = 1; r < R; ++r) pw[r] = f0[b * R0 + r];
+                        } else if constexpr (s == 1 && USE_F1) {
+                            const int k = j % NSPAN;
+#pragma unroll
+                            for (int r = 1; r < R; ++r) pw[r] = f1[(b * R1 + r) * SP1 + k];
+                        } else {
+                            powers<R>(base, pw);
+                        }
 #pragma unroll
                         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pw[r]);
                         IDft<R, T>::run(v[i]);
