@@ -118,10 +118,11 @@ struct Pass1 {
         const int64_t u = a.unit0 + ul;
 
         PhaseCoef coef{};
-        int64_t klo = 0, khi = -1;
+        // bins of the non-negative half: k < N/2 <= 2^21, 32-bit arithmetic
+        int klo = 0, khi = -1;
         const cx<T>* w = nullptr;
         const cx<T>* qin = nullptr;
-        int64_t blo = 0, bhi = 0;  // P1_BAND: the transformed band [blo, bhi)
+        int blo = 0, bhi = 0;      // P1_BAND: the transformed band [blo, bhi)
         cx<T>* qout = nullptr;     // P1_BAND: product rows [k1][k2], k1 < N1/2
         if constexpr (RAW) {
             qin = (const cx<T>*)a.raw_in + u * N;
@@ -169,7 +170,7 @@ struct Pass1 {
                         if constexpr (!RAW) {
 #pragma unroll
                             for (int r = 0; r < R / 2; ++r) {
-                                const int64_t k = (j + r * (N1 / R)) * (int64_t)N2 + k2;
+                                const int k = (j + r * (N1 / R)) * N2 + (int)k2;
                                 wk[r] = w[(k >= klo && k <= khi) ? k : 0];
                             }
                         }
@@ -181,7 +182,7 @@ struct Pass1 {
                             } else {
                                 v[i][r] = cx<T>{T(0), T(0)};
                                 if (r < R / 2) {  // k1 < N1/2: non-negative frequencies only
-                                    const int64_t k = k1 * N2 + k2;
+                                    const int k = (int)k1 * N2 + (int)k2;
                                     if (k >= klo && k <= khi) {
                                         cx<T> rotor;
                                         if constexpr (PH == 0) {

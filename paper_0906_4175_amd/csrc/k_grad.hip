@@ -98,7 +98,8 @@ __global__ void __launch_bounds__(NT) k_snr_grad(int64_t n, double df, double se
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int64_t k = k_lo + tid; k <= khi; k += NT) {
+    const int khi32 = (int)khi;  // bins < N/2 <= 2^21
+    for (int k = k_lo + tid; k <= khi32; k += NT) {
         const double kd = (double)k;
         const double u = inv_cbrt_f64_full(kd);
         double ph = series5(g.b, u) + fma(bt, kd, -0.125);
@@ -176,7 +177,8 @@ __global__ void __launch_bounds__(NT) k_metric(int64_t n, double df, int k_lo, c
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int64_t k = k_lo + tid; k <= khi; k += NT) {
+    const int khi32 = (int)khi;  // bins < N/2 <= 2^21
+    for (int k = k_lo + tid; k <= khi32; k += NT) {
         const double kd = (double)k;
         const double u = inv_cbrt_f64_full(kd);
         const double u7 = u * u * u * u * u * u * u;
