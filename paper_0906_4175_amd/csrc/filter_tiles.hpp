@@ -107,12 +107,25 @@ struct Pass1 {
     static constexpr bool USE_T1 = NS >= 2 && sizeof(T) == 4;
     static constexpr int R1 = NS >= 2 ? radix_at(N1, 1) : 1;
     static constexpr int T1 = USE_T1 ? 16 * R1 : 0;
-    static constexpr size_t SMEM = (size_t)(N1 * C + TW + T1) * sizeof(cx<T>);
+    // XS: the stages exchange real parts, then imaginary parts, through N1 C
+    // scalars (half the LDS); every thread holds EPT = C N1 / NT values at every
+    // stage, so the next stage's inputs are read into one array of that size.
+    static constexpr bool all_full() {
+        for (int s = 0; s < NS; ++s)
+            if ((C * N1 / radix_at(N1, s)) % NT != 0) return false;
+        return true;
+    }
+    static constexpr bool XS = NS > 1 && all_full();
+    static constexpr int EPT = C * N1 / NT;
+    static constexpr size_t BUF_BYTES = (size_t)N1 * C * (XS ? sizeof(T) : sizeof(cx<T>));
+    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1) * sizeof(cx<T>);
 
     __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
         cx<T>* buf = (cx<T>*)smem;
-        cx<T>* tw = buf + N1 * C;
+        T* fbuf = (T*)smem;
+        cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);
         cx<T>* t1 = tw + TW;  // [k][r]
+        [[maybe_unused]] cx<T> carry[XS ? EPT : 1];
         const int tid = threadIdx.x;
         const int k2_0 = tile * C;
         const int64_t u = a.unit0 + ul;
@@ -201,9 +214,14 @@ struct Pass1 {
                         }
                     } else {
                         const int k = j % NSPAN;
-                        const cx<T>* src = buf + j * C + c;
+                        if constexpr (XS) {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) v[i][r] = src[r * (N1 / R) * C];
+                            for (int r = 0; r < R; ++r) v[i][r] = carry[i * R + r];
+                        } else {
+                            const cx<T>* src = buf + j * C + c;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) v[i][r] = src[r * (N1 / R) * C];
+                        }
                         cx<T> p[R];
                         if constexpr (s == 1 && USE_T1) {
                             static_assert(NSPAN == 16 && R == R1, "stage-1 table shape");
@@ -237,6 +255,36 @@ struct Pass1 {
                         cx<T>* dst = inter + (int64_t)j * N2 + k2_0 + c;
 #pragma unroll
                         for (int r = 0; r < R; ++r) dst[(int64_t)r * NSPAN * N2] = v[i][r];
+                    }
+                }
+            } else if constexpr (XS) {
+                constexpr int RN = radix_at(N1, s + 1);
+                constexpr int BPTN = C * N1 / RN / NT;
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i) {
+                        const int bf = tid + i * NT;
+                        const int c = bf % C;
+                        const int j = bf / C;
+                        const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
+                        T* dst = fbuf + idxD * C + c;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) dst[r * NSPAN * C] = part ? v[i][r].y : v[i][r].x;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < BPTN; ++i) {
+                        const int bf = tid + i * NT;
+                        const int c = bf % C;
+                        const int j = bf / C;
+                        const T* src = fbuf + j * C + c;
+#pragma unroll
+                        for (int r = 0; r < RN; ++r) {
+                            if (part) carry[i * RN + r].y = src[r * (N1 / RN) * C];
+                            else carry[i * RN + r].x = src[r * (N1 / RN) * C];
+                        }
                     }
                 }
             } else {
