@@ -319,7 +319,7 @@ def run_gpu(args):
         # time every built plan on this workload and install the fastest (untimed)
         from paper_0906_4175_amd import tune
         tb = mf.spa_bank(grid, mc, eta, Sn, args.precision)
-        r = tune.tune(grid, tb, S64 if args.precision == "fp64" else S32, Sn, args.precision, units=(32, 64, 128),
+        r = tune.tune(grid, tb, S64 if args.precision == "fp64" else S32, Sn, args.precision, units=(256, 512, 1024),
                       steps=2, warmup=1, install=True)
         tuned = {"plan": r["best"], "ms": round(r["best_ms"], 4), "candidates": len(r["table"])}
         del tb

@@ -208,12 +208,14 @@ Plan default_plan(int log2n, mf_precision prec) {
     MF_SHAPES(MF_FIRST)
 #undef MF_FIRST
     if (!found) return p;
-    // About 1 GiB of intermediates per batch: long launches amortise the
-    // launch and ramp cost (measured best for N = 2^20 on MI355X).  Separate
-    // pass-1 / pass-2 launches measured slightly faster than the pipelined
-    // step at this batch size, so the step is off by default.
+    // About 8 GiB of intermediates per batch (of the 288 GB of HBM): every
+    // pass boundary drains and refills the GPU, so few long launches win.
+    // Measured on MI355X (N = 2^20, FP32): 128 units 275k, 512 units 293k
+    // units/s; (N = 2^22): 32 units 51k, 128 units 56k.  Separate pass-1 /
+    // pass-2 launches measured faster than the pipelined step at large
+    // batches, so the step is off by default.
     const size_t bytes_per_unit = ((size_t)1 << log2n) * cx_bytes(prec);
-    size_t u = ((size_t)1 << 30) / bytes_per_unit;
+    size_t u = ((size_t)8 << 30) / bytes_per_unit;
     p.units = (int)(u < 1 ? 1 : (u > 4096 ? 4096 : u));
     p.fused = false;
     return p;

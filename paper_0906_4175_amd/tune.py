@@ -68,7 +68,7 @@ def gpu_arch() -> str:
     return getattr(props, "gcnArchName", props.name).split(":")[0]
 
 
-def tune(grid, bank, stilde, Sn, precision="fp32_ph64", units=(16, 32, 64, 128), steps: int = 3,
+def tune(grid, bank, stilde, Sn, precision="fp32_ph64", units=(128, 256, 512, 1024), steps: int = 3,
          warmup: int = 1, install: bool = True, cache: str | None = None, verbose: bool = False) -> dict:
     """Time every candidate plan on this workload; return {"best": plan, "table": rows}."""
     import torch
