@@ -133,8 +133,7 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
  * pass-2 work-group, pass-1 threads, pass-2 threads, units per batch, flags}.
  * flags bit 0: pass 1 of batch b and pass 2 of batch b-1 share a launch;
  * bit 1: the pass-2 stages exchange real and imaginary parts one after the
- * other through half the LDS (more work-groups per CU).  The two bits
- * exclude each other.
+ * other through half the LDS (more work-groups per CU).
  */
 mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 

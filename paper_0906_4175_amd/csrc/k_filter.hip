@@ -45,10 +45,10 @@ __global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
 // launch.  The two roles touch disjoint intermediates and disjoint units, and
 // their work-groups are interleaved so that every CU mixes the store-bound
 // pass 1 with the arithmetic-bound pass 2.
-template <typename T, int PH, int N1, int N2, int C, int B, int NT>
+template <typename T, int PH, int N1, int N2, int C, int B, int NT, bool XS>
 __global__ void __launch_bounds__(NT) k_step(FilterArgs a1, FilterArgs a2) {
     using P1 = Pass1<T, PH, P1_PRODUCT, N1, N2, C, NT>;
-    using P2 = Pass2<T, false, N1, N2, B, NT>;
+    using P2 = Pass2<T, false, N1, N2, B, NT, 16, XS>;
     __shared__ __align__(16) char smem[MaxSz<P1::SMEM, P2::SMEM>::value];
     constexpr int W1 = N2 / C;  // pass-1 tiles per unit
     constexpr int W2 = N1 / B;  // pass-2 tiles per unit
@@ -175,7 +175,7 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
         Plan q{};                                                                                      \
         fill(q, N1, N2, C, B, R2, XS);                                                                 \
         q.units = 0;                                                                                   \
-        for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 && !XS ? 2 : 1); ++f) {                        \
+        for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 ? 2 : 1); ++f) {                               \
             q.fused = f == 1;                                                                          \
             if (out && n < cap) out[n] = q;                                                            \
             ++n;                                                                                       \
@@ -189,7 +189,7 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
 bool plan_supported(const Plan& q, mf_precision prec) {
 #define MF_MATCH(T, N1, N2, C, B, R2, XS)                                                                  \
     if (want(prec, std::is_same<T, double>::value) && q.n1 == N1 && q.n2 == N2 && q.c1 == C && q.b2 == B && \
-        q.nt2 == clamp_threads(B * N2 / R2) && q.split == (XS != 0) && !(q.fused && XS))                     \
+        q.nt2 == clamp_threads(B * N2 / R2) && q.split == (XS != 0))                                         \
         return true;
     MF_SHAPES(MF_MATCH)
 #undef MF_MATCH
@@ -287,13 +287,13 @@ hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const Filter
     return hipErrorInvalidValue;
 }
 
-template <typename T, int PH, int N1, int N2, int C, int B>
+template <typename T, int PH, int N1, int N2, int C, int B, bool XS>
 static hipError_t run_step(const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
     constexpr int NT1 = clamp_threads(C * N1 / 16), NT2 = clamp_threads(B * N2 / 16);
     if constexpr (NT1 == NT2) {
         const int64_t blocks = a1.units * (N2 / C) + a2.units * (N1 / B);
         if (blocks <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_step<T, PH, N1, N2, C, B, NT1>), dim3((unsigned)blocks), dim3(NT1), 0, s, a1, a2);
+        hipLaunchKernelGGL((k_step<T, PH, N1, N2, C, B, NT1, XS>), dim3((unsigned)blocks), dim3(NT1), 0, s, a1, a2);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -303,9 +303,10 @@ static hipError_t run_step(const FilterArgs& a1, const FilterArgs& a2, hipStream
 hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
 #define MF_ST(T, N1, N2, C, B, R2, XS)                                                                         \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B &&   \
-        R2 == 16 && !XS) {                                                                                    \
-        if (std::is_same<T, float>::value && prec == MF_FP32) return run_step<float, 1, N1, N2, C, B>(a1, a2, s); \
-        return run_step<T, 0, N1, N2, C, B>(a1, a2, s);                                                       \
+        R2 == 16 && p.split == (XS != 0)) {                                                                   \
+        if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
+            return run_step<float, 1, N1, N2, C, B, XS != 0>(a1, a2, s);                                       \
+        return run_step<T, 0, N1, N2, C, B, XS != 0>(a1, a2, s);                                               \
     }
     MF_SHAPES(MF_ST)
 #undef MF_ST

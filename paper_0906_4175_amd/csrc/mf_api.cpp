@@ -179,7 +179,7 @@ Plan select_plan(int log2n, mf_precision prec) {
     if (const char* e = getenv("MF_FUSED")) {
         const int b16 = p.b2 * p.n2 / 16;
         const int nt16 = b16 < 64 ? 64 : (b16 > 1024 ? 1024 : b16);
-        p.fused = e[0] == '1' && p.nt1 == p.nt2 && p.nt2 == nt16 && !p.split;
+        p.fused = e[0] == '1' && p.nt1 == p.nt2 && p.nt2 == nt16;
     }
     if (const char* e = getenv("MF_UNITS")) {
         const long v = strtol(e, nullptr, 10);

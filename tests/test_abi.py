@@ -156,12 +156,13 @@ def test_plan_candidates_and_set_plan_validation(lib):
     # flags: bit 0 pipelined step, bit 1 split pass-2 exchange (the 2^20 FP32 default)
     assert out[7] == 2
     flags = {(tuple(buf[8 * i: 8 * i + 6]), buf[8 * i + 7]) for i in range(n)}
-    assert ((256, 4096, 16, 1, 256, 256), 2) in flags and ((256, 4096, 16, 1, 256, 256), 0) in flags
-    assert ((256, 4096, 16, 1, 256, 256), 3) not in flags
+    for f in (0, 1, 2, 3):  # separate or pipelined launches, complex or split exchange
+        assert ((256, 4096, 16, 1, 256, 256), f) in flags
     bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 4)  # unknown flag bit
     assert lib.mf_set_plan(C.byref(g), 1, bad) == -1
-    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 3)  # pipelined step with the split exchange
-    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
+    both = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 3)  # pipelined step with the split exchange
+    assert lib.mf_set_plan(C.byref(g), 1, both) == 0
+    assert lib.mf_filter_plan(C.byref(g), 1, out) == 0 and out[7] == 3
     bad = (C.c_int32 * 8)(1024, 1024, 8, 4, 512, 256, 16, 2)  # split exchange not built for this shape
     assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
     good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 0)
