@@ -372,8 +372,12 @@ def test_batching_and_fusion_bitwise_invariant(mf, prec):
     xs = "256,4096,16,1,16" if prec != "fp64" else "256,4096,8,1,16"
     split = _with_env({"MF_PLAN": xs + ",1", "MF_UNITS": "5"}, lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
     whole = _with_env({"MF_PLAN": xs + ",0", "MF_UNITS": "64"}, lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
+    # and with the pipelined step (FP32 shape; FP64 work-group sizes differ, so it runs separate launches)
+    piped = _with_env({"MF_PLAN": xs + ",1", "MF_UNITS": "7", "MF_FUSED": "1"},
+                      lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
     for f in ("rho", "j", "n_above"):
         assert torch.equal(split[f].cpu(), whole[f].cpu()), f
+        assert torch.equal(piped[f].cpu(), whole[f].cpu()), f
     if prec != "fp64":
         other = _with_env({"MF_PLAN": "1024,1024,8,4", "MF_UNITS": "16"},
                           lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
