@@ -337,8 +337,18 @@ struct Pass2 {
     static constexpr int RL = radix_at(N2, NS - 1, MAXR);
     static constexpr int SPAN_L = span_before(N2, NS - 1, MAXR);
     static constexpr bool DEFER = !F64 && !RAW && B * N2 / RL == NT;
+    // TAB2 (FP64, 4096-point rows, three radix-16 stages, one row per
+    // work-group): stage 0 applies the whole four-step factor
+    // t^{k2} = t^j t^{256 r}, so the factors of stages 1 and 2, w^(k r), no
+    // longer depend on the row and come from tables (stage 1: 15 x 16 entries
+    // in LDS; stage 2: 15 x 256 entries in the workspace, filled once per call)
+    // instead of products of powers.  In FP32 the table loads measured slower
+    // than the products they replace.
+    static constexpr bool TAB2 =
+        F64 && !RAW && N2 == kTw2Span * kTw2Radix && MAXR == 16 && B == 1 && NT == 256 && NS == 3;
+    static constexpr int TWL = TAB2 ? 15 * 16 : TW;
     static constexpr size_t BUF_BYTES = (size_t)B * PN2 * (SPLIT ? sizeof(T) : sizeof(cx<T>));
-    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + B * NS + B * R0) * sizeof(cx<T>) +
+    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TWL + B * NS + B * R0) * sizeof(cx<T>) +
                                    (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
 
@@ -355,8 +365,8 @@ struct Pass2 {
     __device__ static void run(const FilterArgs& a, char* smem, int rb, int64_t ul) {
         cx<T>* buf = (cx<T>*)smem;
         T* fbuf = (T*)smem;  // SPLIT: [B][PN2] scalars
-        cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);
-        cx<T>* trow = tw + TW;  // [B][NS]: t^{weight_s} per row
+        cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);  // TAB2: [r - 1][k] stage-1 factors
+        cx<T>* trow = tw + TWL;  // [B][NS]: t^{weight_s} per row
         cx<T>* pow0 = trow + B * NS;  // [B][R0]: (t^{weight_0})^r, the stage-0 factors of each row
         unsigned long long* red_key = (unsigned long long*)(pow0 + B * R0);
         double* red_zz = (double*)(red_key + NWAVE);
@@ -367,7 +377,7 @@ struct Pass2 {
         const int64_t u = a.unit0 + ul;
         const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
 
-        if (tid < B * NS) {
+        if (!TAB2 && tid < B * NS) {
             const int b = tid / NS, st = tid % NS;
             const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st, MAXR);  // < N
             trow[b * NS + st] = root_of_unity((T)m / (T)N);
@@ -430,9 +440,18 @@ struct Pass2 {
                         const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
 #pragma unroll
                         for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
-                        // stage 0 has no stage twiddle: its factors are the row's table
+                        if constexpr (TAB2) {
+                            // input r is k2 = j + PER_ROW r: t^{k2} = t^j (t^{PER_ROW})^r
+                            const int64_t m = ((int64_t)(rb * B + b) * j) & (N - 1);
+                            const cx<T> tj = root_of_unity((T)m / (T)N);
+                            v[i][0] = cmul(v[i][0], tj);
 #pragma unroll
-                        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pow0[b * R0 + r]);
+                            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], cmul(pow0[b * R0 + r], tj));
+                        } else {
+                            // stage 0 has no stage twiddle: its factors are the row's table
+#pragma unroll
+                            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pow0[b * R0 + r]);
+                        }
                     } else {
                         const int k = j % NSPAN;
                         if constexpr (SPLIT) {
@@ -444,14 +463,33 @@ struct Pass2 {
                             for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
                         }
                         cx<T> p[R];
-                        powers<R>(cmul(tw[tw_offset(N2, s, MAXR) + k], trow[b * NS + s]), p);
+                        if constexpr (TAB2 && s == 1) {
+#pragma unroll
+                            for (int r = 1; r < R; ++r) p[r] = tw[(r - 1) * NSPAN + k];
+                        } else if constexpr (TAB2 && s == 2) {
+                            const cx<T>* t2 = (const cx<T>*)a.tw2;
+#pragma unroll
+                            for (int r = 1; r < R; ++r) p[r] = t2[(r - 1) * NSPAN + k];
+                        } else {
+                            powers<R>(cmul(tw[tw_offset(N2, s, MAXR) + k], trow[b * NS + s]), p);
+                        }
 #pragma unroll
                         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], p[r]);
                     }
                     IDft<R, T>::run(v[i]);
                 }
             }
-            if constexpr (s == 0) fill_stage_twiddles<T, N2, MAXR>(tw, tid, NT);
+            if constexpr (s == 0) {
+                if constexpr (TAB2) {
+                    // stage-1 factors e^{2 pi i k r / 256}, k < 16, from exactly reduced arguments
+                    for (int q = tid; q < 15 * 16; q += NT) {
+                        const int r = q / 16 + 1, k = q % 16;
+                        tw[q] = root_of_unity((T)((k * r) & 255) / (T)256);
+                    }
+                } else {
+                    fill_stage_twiddles<T, N2, MAXR>(tw, tid, NT);
+                }
+            }
             if constexpr (s == NS - 1) {
 #pragma unroll
                 for (int i = 0; i < BPT; ++i) {

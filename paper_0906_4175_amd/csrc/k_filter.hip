@@ -241,6 +241,9 @@ FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t 
     if (prec != MF_FP64) off = align256(off + (size_t)n_units * 4);
     L.off_part = off;
     if (prec == MF_FP64) off = align256(off + (size_t)n_units * (size_t)(p.n1 / p.b2) * sizeof(Partial64));
+    L.off_tw2 = off;
+    if (pass2_uses_tw2(prec, p.n2, p.b2, p.nt2))
+        off = align256(off + (size_t)(kTw2Radix - 1) * kTw2Span * cx_bytes(prec));
     L.total = off;
     return L;
 }
@@ -311,6 +314,26 @@ hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, c
     MF_SHAPES(MF_ST)
 #undef MF_ST
     return hipErrorInvalidValue;
+}
+
+// tw2[(r - 1) * span + k] = e^{2 pi i k r / (span R)}, each from its exactly
+// reduced argument
+template <typename T>
+__global__ void k_tw2_fill(cx<T>* tw2) {
+    constexpr int M = kTw2Span * kTw2Radix;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (kTw2Radix - 1) * kTw2Span) return;
+    const int r = q / kTw2Span + 1, k = q % kTw2Span;
+    tw2[q] = root_of_unity((T)((k * r) & (M - 1)) / (T)M);
+}
+
+hipError_t launch_tw2_fill(mf_precision prec, void* tw2, hipStream_t s) {
+    constexpr int total = (kTw2Radix - 1) * kTw2Span;
+    if (prec == MF_FP64)
+        hipLaunchKernelGGL(k_tw2_fill<double>, dim3((total + 255) / 256), dim3(256), 0, s, (cx<double>*)tw2);
+    else
+        hipLaunchKernelGGL(k_tw2_fill<float>, dim3((total + 255) / 256), dim3(256), 0, s, (cx<float>*)tw2);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Plan& p, mf_precision prec, const FilterArgs& a, mf_peak* peaks, hipStream_t s) {

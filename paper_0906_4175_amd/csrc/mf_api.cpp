@@ -395,10 +395,15 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
     a.rho = rho_dev;
     a.ev_keys = ev_keys;
     a.ev_log2w = ev_log2w;
+    a.tw2 = ws + L.off_tw2;
 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);
     if (e != hipSuccess) return hip_fail(e, "mf_filter weights");
+    if (mf::pass2_uses_tw2(prec, p.n2, p.b2, p.nt2)) {
+        e = mf::launch_tw2_fill(prec, ws + L.off_tw2, s);
+        if (e != hipSuccess) return hip_fail(e, "mf_filter stage table");
+    }
     const int64_t upb = L.units_per_batch;
     const int64_t nb = (a.n_units + upb - 1) / upb;
     auto batch = [&](mf::FilterArgs& x, int64_t b, int buf) {

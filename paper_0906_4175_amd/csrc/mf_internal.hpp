@@ -42,9 +42,18 @@ size_t cx_bytes(mf_precision prec);
 
 // Workspace carve-up of mf_filter.
 struct FilterLayout {
-    size_t off_w, off_inter, inter_bytes, off_keys, off_counts, off_part, total;
+    size_t off_w, off_inter, inter_bytes, off_keys, off_counts, off_part, off_tw2, total;
     int64_t units_per_batch;
 };
+// FP64 pass 2 of the 4096-point rows (three radix-16 stages, one row per
+// work-group) applies the whole four-step factor at stage 0 and reads the last
+// stage's factors w^(k r), k < 256, 1 <= r < 16, from a constant table in the
+// workspace.
+constexpr int kTw2Span = 256, kTw2Radix = 16;
+inline bool pass2_uses_tw2(mf_precision prec, int n2, int b2, int nt2) {
+    return prec == MF_FP64 && n2 == kTw2Span * kTw2Radix && b2 == 1 && nt2 == 256;
+}
+hipError_t launch_tw2_fill(mf_precision prec, void* tw2, hipStream_t s);
 FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg);
 
 struct FilterArgs {
@@ -72,6 +81,7 @@ struct FilterArgs {
     // sample at or above the threshold (see event_key32 / event_key64)
     unsigned long long* ev_keys;  // [n_units][n >> ev_log2w], unit u = s * n_tmpl + t
     int32_t ev_log2w;
+    const void* tw2;              // [kTw2Radix - 1][kTw2Span] last-stage factors (see pass2_uses_tw2)
 };
 
 // Workspace carve-up of mf_filter_chisq (band mode).
