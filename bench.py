@@ -19,7 +19,6 @@ from __future__ import annotations
 import argparse
 import contextlib
 import gc
-import hashlib
 import json
 import math
 import os
@@ -37,9 +36,6 @@ METRIC = "templates×segments/s at 2^20-pt IFFT; HBM GB/s fraction; vs FP64 path
 UNIT = "templates×segments/s"
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f)
-                  for f in ("k_filter.hip", "k_filter_chisq.hip", "filter_tiles.hpp", "mf_device.hpp")]
-
 
 @contextlib.contextmanager
 def quiet_gc():
@@ -54,11 +50,8 @@ def quiet_gc():
 
 
 def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_0906_4175_amd.profile_summary import kernel_hash as khash
+    return khash()
 
 
 def workload_bank(cfg: int):

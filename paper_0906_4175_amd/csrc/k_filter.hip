@@ -8,10 +8,10 @@
 // stationary-phase rotor e^{+i Psi_k} of the template in registers, forms
 // q_k = e^{+i Psi_k} w_k (w_k = 4 df f_k^{-7/6} s_k / S_k, the template
 // amplitude folded into the data weight), runs the N1-point column transforms
-// in registers and LDS, applies the four-step twiddle and writes the
-// intermediate once.  Columns only carry data for k1 < N1/2 (negative
-// frequencies are zero) and inside [k_lo, k_hi].
-// Pass 2 (one work-group per B rows j1) reads each row once, runs the
+// in registers and LDS and writes the intermediate once.  Columns only carry
+// data for k1 < N1/2 (negative frequencies are zero) and inside [k_lo, k_hi].
+// Pass 2 (one work-group per B rows j1) reads each row once, applies the
+// four-step factor e^{2 pi i j1 k2 / N} inside its stage twiddles, runs the
 // N2-point row transforms and never writes z: it squares |z_j|, counts
 // threshold crossings and reduces the maximum with the lowest index.
 // Both passes are Stockham auto-sort transforms (radix 16 stages, remainder
