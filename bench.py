@@ -486,7 +486,7 @@ def main():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--precision", default="fp32_ph64", choices=["fp32_ph64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=10)
-    ap.add_argument("--timing-stride", type=int, default=7)  # odd: samples both pass kinds
+    ap.add_argument("--timing-stride", type=int, default=1)  # 1: every transform launch is timed
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-procs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
