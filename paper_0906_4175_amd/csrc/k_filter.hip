@@ -141,10 +141,11 @@ static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 102
     X(float, 64, 128, 16, 32, 16, 0) X(float, 128, 128, 16, 32, 16, 0) X(float, 128, 256, 16, 16, 16, 0)            \
     X(float, 256, 256, 16, 16, 16, 0) X(float, 256, 512, 16, 8, 16, 0) X(float, 512, 512, 16, 8, 16, 0)             \
     X(float, 512, 1024, 16, 4, 16, 0) X(float, 256, 4096, 16, 1, 16, 1) X(float, 256, 4096, 16, 1, 16, 0)           \
-    X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 8, 1, 16, 0) X(float, 1024, 4096, 8, 1, 16, 1)          \
+    X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 16, 1, 16, 1) X(float, 1024, 4096, 16, 1, 16, 0)        \
+    X(float, 1024, 4096, 8, 1, 16, 0) X(float, 1024, 4096, 8, 1, 16, 1)                                           \
     X(float, 1024, 1024, 8, 4, 16, 0) X(float, 1024, 1024, 16, 8, 16, 0) X(float, 1024, 1024, 16, 4, 16, 0)         \
     X(float, 512, 2048, 16, 2, 16, 0) X(float, 2048, 512, 8, 8, 16, 0) X(float, 2048, 2048, 8, 2, 16, 0)            \
-    X(float, 1024, 4096, 16, 1, 16, 0) X(float, 512, 8192, 16, 1, 16, 0) X(float, 256, 4096, 16, 1, 8, 0)           \
+    X(float, 512, 8192, 16, 1, 16, 0) X(float, 256, 4096, 16, 1, 8, 0)                                             \
     X(float, 1024, 4096, 8, 1, 8, 0)                                                                              \
     X(double, 32, 32, 8, 32, 16, 0) X(double, 32, 64, 8, 32, 16, 0) X(double, 64, 64, 8, 64, 16, 0)                 \
     X(double, 64, 128, 8, 32, 16, 0) X(double, 128, 128, 8, 32, 16, 0) X(double, 128, 256, 8, 16, 16, 0)            \
@@ -211,7 +212,7 @@ Plan default_plan(int log2n, mf_precision prec) {
     // About 8 GiB of intermediates per batch (of the 288 GB of HBM): every
     // pass boundary drains and refills the GPU, so few long launches win.
     // Measured on MI355X (N = 2^20, FP32): 128 units 275k, 512 units 293k
-    // units/s; (N = 2^22): 32 units 51k, 128 units 56k.  Separate pass-1 /
+    // units/s; (N = 2^22, 1024x4096, C = 8): 32 units 51k, 128 units 56k.  Separate pass-1 /
     // pass-2 launches measured faster than the pipelined step at large
     // batches, so the step is off by default.
     const size_t bytes_per_unit = ((size_t)1 << log2n) * cx_bytes(prec);

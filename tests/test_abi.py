@@ -171,7 +171,7 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert lib.mf_set_plan(C.byref(g), 1, None) == 0
     g22 = _grid(n=1 << 22)
     assert lib.mf_filter_plan(C.byref(g22), 1, out) == 0
-    assert list(out)[:4] == [1024, 4096, 8, 1] and out[7] == 0
+    assert list(out)[:4] == [1024, 4096, 16, 1] and out[7] == 2
 
 
 def test_tune_cache_corrupt_and_foreign(tmp_path):
