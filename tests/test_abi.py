@@ -152,7 +152,7 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert list(out)[:4] == [1024, 1024, 8, 4] and out[6] == 16
     assert lib.mf_set_plan(C.byref(g), 1, None) == 0
     assert lib.mf_filter_plan(C.byref(g), 1, out) == 0
-    assert list(out)[:4] == [256, 4096, 16, 1]
+    assert list(out)[:4] == [256, 4096, 32, 1]
     # flags: bit 0 pipelined step, bit 1 split pass-2 exchange (the 2^20 FP32 default)
     assert out[7] == 2
     flags = {(tuple(buf[8 * i: 8 * i + 6]), buf[8 * i + 7]) for i in range(n)}
