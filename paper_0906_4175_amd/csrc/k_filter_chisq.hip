@@ -20,6 +20,10 @@
 // intermediate and the weights instead of p intermediates.
 #include "filter_tiles.hpp"
 
+#ifndef MF_BAND_WAVES
+#define MF_BAND_WAVES 4
+#endif
+
 namespace mf {
 
 // Peak record of one pass-2 work-group in band mode: max |z|^2 (lowest index
@@ -365,8 +369,18 @@ __global__ void __launch_bounds__(NT) k_pass1_band(FilterArgs a) {
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
 
+// FP32 radix-16 rows, one row per work-group: at least 4 waves per SIMD (128
+// VGPRs).  The compiler then spills a few registers, which measured 10% faster
+// than 3 waves at 164 VGPRs.  (Shapes with several rows per work-group are
+// held below 4 waves by LDS anyway.)
+template <typename T, int B, int R2>
+constexpr int band_min_waves() {
+    return MF_BAND_WAVES > 0 && sizeof(T) == 4 && R2 == 16 && B == 1 ? MF_BAND_WAVES : 1;
+}
+
 template <typename T, int N1, int N2, int B, int NT, int R2>
-__global__ void __launch_bounds__(NT) k_pass2_band(FilterArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(band_min_waves<T, B, R2>(), 8)))
+k_pass2_band(FilterArgs a) {
     using P = Pass2Band<T, N1, N2, B, NT, R2>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
