@@ -22,6 +22,26 @@
 
 namespace mf {
 
+// 1/x for a positive normal x: hardware estimate, then two Newton steps
+// (r <- r + r (1 - x r)), each doubling the correct bits, to full FP64 precision
+// (within an ulp) without the special-case handling of an IEEE division.
+__device__ __forceinline__ double rcp_pos_f64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// sqrt(x) for a positive normal x: y = 1/sqrt(x) from the hardware estimate and
+// two Newton steps (y <- y (3 - x y^2) / 2), then sqrt(x) = x y with one
+// correction (s + y (x - s^2) / 2).
+__device__ __forceinline__ double sqrt_pos_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    const double s = x * y;
+    return fma(0.5 * y, fma(-s, s, x), s);
+}
+
 struct GradCoef {
     double b[4];   // u^1, u^2, u^3, u^5 coefficients (cycles)
     double dm[4];  // d b / d M_c
@@ -106,8 +126,8 @@ __global__ void __launch_bounds__(NT) k_snr_grad(int64_t n, double df, double se
         ph -= rint(ph);
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);
-        const double a = amp0 * u * u * u * sqrt(u);  // f^{-7/6} = df^{-7/6} u^{7/2}
-        const double invS = 1.0 / Sn[k];
+        const double a = amp0 * u * u * u * sqrt_pos_f64(u);  // f^{-7/6} = df^{-7/6} u^{7/2}
+        const double invS = rcp_pos_f64(Sn[k]);                // S > 0 inside the band
         const cx<T> sv = s[k];
         const double wr = (double)sv.x * invS * a, wi = (double)sv.y * invS * a;
         const double tr = wr * cs - wi * sn, ti = wr * sn + wi * cs;  // a w e^{i Psi}
