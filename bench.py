@@ -296,6 +296,11 @@ def run_gpu(args):
         graph.replay()
         torch.cuda.synchronize()
         same = bool(torch.equal(peaks, eager))
+        # warm-up replays, as the eager leg has warm-up steps: the clock ramps
+        # back up after the host-side capture
+        for _ in range(3):
+            graph.replay()
+        torch.cuda.synchronize()
         with quiet_gc():
             t0 = time.perf_counter()
             for _ in range(steps):
