@@ -239,7 +239,8 @@ def run_gpu(args):
             r = mf.filter_events(grid, bank, st, Sn, prec, threshold=threshold, log2_window=log2w, workspace=ws)
             c, _ = mf.chisq_events(grid, bank, st, Sn, P, r["seg_events"], prec, p_bands=p_bands)
             return r, c
-        step()
+        for _ in range(3):  # warm-up steps, as in the other legs
+            step()
         torch.cuda.synchronize()
         with quiet_gc():
             t0 = time.perf_counter()
@@ -265,7 +266,8 @@ def run_gpu(args):
         bank = mf.spa_bank(g4, mc, eta, Sn4, prec)
         ws = torch.empty(mf.filter_workspace_bytes(g4, prec, bank.n_tmpl, 1), dtype=torch.uint8, device=dev)
         peaks = torch.empty(2 * bank.n_tmpl, dtype=torch.float64, device=dev)
-        mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
+        for _ in range(3):  # warm-up steps
+            mf.filter(g4, bank, st4, Sn4, prec, workspace=ws, peaks=peaks)
         torch.cuda.synchronize()
         with quiet_gc():
             t0 = time.perf_counter()
@@ -326,10 +328,10 @@ def run_gpu(args):
     graph = measure_graph(args.precision, args.graph_steps) if args.graph_steps > 0 else None
     fp64 = None
     if args.fp64_steps > 0:
-        fp64 = measure("fp64", args.fp64_steps, 1, args.timing_stride)
+        fp64 = measure("fp64", args.fp64_steps, 3, args.timing_stride)
     chisq = None
     if args.chisq_steps > 0:
-        chisq = measure_chisq(args.precision, args.chisq_steps, 1, args.timing_stride, args.chisq_bands)
+        chisq = measure_chisq(args.precision, args.chisq_steps, 2, args.timing_stride, args.chisq_bands)
     events = None
     if args.events_steps > 0:
         e32 = measure_events(args.precision, args.events_steps, args.events_threshold, args.events_log2w,
