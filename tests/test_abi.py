@@ -227,3 +227,17 @@ def test_chisq_entry_points_validation(lib):
     su = L.MfFilterOpts(math.inf, 0, 0, vp(256), 2)  # series without output arrays
     assert lib.mf_filter_chisq(*fargs(w16, opts=C.byref(su))) == -1
     assert b"chisq_series" in lib.mf_last_error()
+
+
+def test_kernel_hash_ignores_comments_and_whitespace(tmp_path, monkeypatch):
+    """Profiles stay valid across comment edits and go stale on code edits."""
+    from paper_0906_4175_amd import profile_summary as ps
+    code = "__global__ void k(float* x) { x[threadIdx.x] *= 2.0f; }\n"
+    f = tmp_path / "k.hip"
+    monkeypatch.setattr(ps, "KERNEL_SOURCES", [str(f)])
+    f.write_text(code)
+    h0 = ps.kernel_hash()
+    f.write_text("// a note\n/* a block\n   comment */\n" + code.replace("{ ", "{\n    ") + "// end\n")
+    assert ps.kernel_hash() == h0
+    f.write_text(code.replace("2.0f", "3.0f"))
+    assert ps.kernel_hash() != h0
