@@ -123,7 +123,10 @@ const char* mf_version(void);
 size_t mf_bank_bytes(int64_t n_tmpl);
 
 /* Bytes of device workspace mf_filter needs for this request (0 on invalid
- * arguments, with mf_last_error set). */
+ * arguments, with mf_last_error set).  The bulk is one batch of
+ * intermediates, min(n_tmpl * n_seg, units per batch) * N complex values: the
+ * default plans batch about 8 GiB (1024 units at N = 2^20 in the FP32 modes),
+ * so a large bank needs about 8 GiB plus N/2+1 complex weights per segment. */
 size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
                                  int64_t n_tmpl, int64_t n_seg);
 
