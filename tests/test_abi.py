@@ -174,6 +174,21 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert list(out)[:4] == [1024, 4096, 16, 1] and out[7] == 2
 
 
+@pytest.mark.parametrize("n, prec, shape, threads, units", [
+    (1 << 20, 1, [256, 4096, 32, 1], [512, 256], 1024),   # FP32 (FP64 phase): 8 GiB of intermediates
+    (1 << 20, 2, [256, 4096, 32, 1], [512, 256], 1024),   # FP32 phase: same plan class
+    (1 << 20, 0, [256, 4096, 16, 1], [256, 256], 512),    # FP64
+    (1 << 22, 1, [1024, 4096, 16, 1], [1024, 256], 256),  # 4 x 2^20 samples
+])
+def test_default_plans(lib, n, prec, shape, threads, units):
+    g = _grid(n=n)
+    assert lib.mf_set_plan(C.byref(g), prec, None) == 0
+    out = (C.c_int32 * 8)()
+    assert lib.mf_filter_plan(C.byref(g), prec, out) == 0
+    assert list(out)[:4] == shape and list(out)[4:6] == threads and out[6] == units
+    assert out[7] == 2  # separate launches, split pass-2 exchange
+
+
 def test_tune_cache_corrupt_and_foreign(tmp_path):
     import warnings
     from paper_0906_4175_amd import tune
