@@ -469,10 +469,12 @@ Plan band_plan(int log2n, mf_precision prec) {
     }
 #undef MF_BFIRST
     if (!found) return p;
-    // About 256 MiB of product and intermediate per batch, so that pass 2
-    // finds most of what pass 1 wrote still in the last-level cache.
+    // About 192 MiB of product and intermediate per batch, so that pass 2
+    // finds what pass 1 wrote still in the 256 MB last-level cache (measured at
+    // 2^20 FP32: 12 units 30.3k, 16 units 31.3k, 21 units 29.7k, 32 units 28.2k
+    // units/s).
     const size_t bytes_per_unit = ((size_t)3 << log2n) / 2 * cx_bytes(prec);
-    size_t u = ((size_t)256 << 20) / bytes_per_unit;
+    size_t u = ((size_t)192 << 20) / bytes_per_unit;
     if (const char* e = getenv("MF_BAND_UNITS")) {
         const long v = strtol(e, nullptr, 10);
         if (v >= 1 && v <= 4096) u = (size_t)v;
