@@ -12,6 +12,12 @@ of the dominant kernel (HIP events on the launch stream during the timed
 steps), the plain FP64 path on the same GPU, and the FP64 oracle timed on the
 host cores over a bounded sample of the same workload.
 
+The default workload is the largest single-GPU one: 32768 uneven templates x 4
+segments of 2^20 samples.  Extra legs: the plain FP64 path and HIP-graph replay
+on the same workload; the single-segment workload (1024 templates x one 2^20
+segment with 5 injections) with the chi^2 band mode, events and the 4 x 2^20
+segment length.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2|3|5]
 """
 from __future__ import annotations
@@ -80,7 +86,22 @@ def _cpu_unit(t: int):
     return out["rho"]
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg: int, seconds: float, max_procs: int):
+    """The FP64 oracle on the host cores, one process per core, over a bounded
+    sample of the workload's templates on its first segment.  The process count
+    is the number of cores this process may run on, capped at max_procs (the
+    host's CPU share for one GPU on the boxes this runs on is 16 cores)."""
     import multiprocessing as mp
 
     import oracle as O
@@ -93,7 +114,8 @@ def cpu_baseline(cfg: int, seconds: float, max_procs: int):
     s = synth.coloured_noise(Sn[k_lo: n // 2], g["df"], k_lo, n // 2 + 1, rng, dtype=np.complex64)
     mc, eta = workload_bank(cfg)
     _CPU.update(n=n, fs=fs, s=s.astype(np.complex128), Sn=Sn, mc=mc, eta=eta)
-    procs = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    affinity = len(os.sched_getaffinity(0))
+    procs = max(1, min(max_procs, affinity))
     t0 = time.perf_counter()
     _cpu_unit(0)
     t_one = time.perf_counter() - t0
@@ -106,7 +128,8 @@ def cpu_baseline(cfg: int, seconds: float, max_procs: int):
     dt = time.perf_counter() - t0
     return {"value": n_units / dt, "unit": UNIT, "cores": procs, "kind": "oracle",
             "sample": f"{n_units} of the {len(mc)} templates x 1 segment (N={n}), FP64 NumPy oracle, "
-                      f"{procs} single-threaded processes, {dt:.1f} s wall"}
+                      f"{procs} single-threaded processes, {dt:.1f} s wall",
+            "affinity_cpus": affinity, "cpu_model": cpu_model()}
 
 
 # ---------------------------------------------------------------------------
@@ -138,34 +161,45 @@ def run_gpu(args):
     import paper_0906_4175_amd as mf
     from paper_0906_4175_amd import _lib as L
 
-    cfg = args.workload
-    wl = synth.WORKLOADS[cfg]
     dev = torch.device("cuda:0")
-    grid = mf.Grid(wl.n, wl.fs, wl.f_low)
-    Sn = mf.psd(grid, device=dev)
-    Sn_h = Sn.cpu().numpy()
-    mc, eta = workload_bank(cfg)
-    n_seg = wl.n_seg
-    k_lo = grid.k_lo
-    rngs = synth.rngs(cfg, n_seg + 1)
-    segs = []
-    for sidx in range(n_seg):
-        segs.append(synth.coloured_noise(Sn_h[k_lo: wl.n // 2], grid.df, k_lo, wl.n // 2 + 1, rngs[sidx],
-                                         dtype=np.complex64))
-    if cfg == 2:
-        # five injections with SNR 8-15, templates synthesised by the library itself
-        injs = synth.injection_params(rngs[-1], 5, wl.n)
-        imc, ieta = synth.mc_eta([i["m1"] for i in injs], [i["m2"] for i in injs])
-        ib = mf.spa_bank(grid, imc, ieta, Sn, "fp32_ph64", materialise=True)
-        ht = ib.htilde.cpu().numpy()
-        for q, inj in enumerate(injs):
-            segs[0] = synth.inject(segs[0], ht[q], inj["snr"] / ib.sigma[q], inj["phi0"], inj["j0"], wl.n)
-    S32 = torch.from_numpy(np.stack(segs)).to(dev)
-    S64 = S32.to(torch.complex128)
 
-    def measure(prec: str, steps: int, warmup: int, stride: int):
-        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
-        st = S64 if prec == "fp64" else S32
+    class Inputs:
+        """A workload's grid, PSD, bank parameters and data spectra, resident on the GPU."""
+
+        def __init__(self, cfg: int):
+            wl = synth.WORKLOADS[cfg]
+            self.cfg, self.wl = cfg, wl
+            self.grid = mf.Grid(wl.n, wl.fs, wl.f_low)
+            self.Sn = mf.psd(self.grid, device=dev)
+            Sn_h = self.Sn.cpu().numpy()
+            self.mc, self.eta = workload_bank(cfg)
+            self.n_seg = wl.n_seg
+            k_lo = self.grid.k_lo
+            rngs = synth.rngs(cfg, wl.n_seg + 1)
+            segs = [synth.coloured_noise(Sn_h[k_lo: wl.n // 2], self.grid.df, k_lo, wl.n // 2 + 1, rngs[i],
+                                         dtype=np.complex64) for i in range(wl.n_seg)]
+            if cfg == 2:
+                # five injections with SNR 8-15, templates synthesised by the library itself
+                injs = synth.injection_params(rngs[-1], 5, wl.n)
+                imc, ieta = synth.mc_eta([i["m1"] for i in injs], [i["m2"] for i in injs])
+                ib = mf.spa_bank(self.grid, imc, ieta, self.Sn, "fp32_ph64", materialise=True)
+                ht = ib.htilde.cpu().numpy()
+                for q, inj in enumerate(injs):
+                    segs[0] = synth.inject(segs[0], ht[q], inj["snr"] / ib.sigma[q], inj["phi0"], inj["j0"], wl.n)
+            self.S32 = torch.from_numpy(np.stack(segs)).to(dev)
+            self._S64 = None
+
+        def stilde(self, prec: str):
+            if prec != "fp64":
+                return self.S32
+            if self._S64 is None:
+                self._S64 = self.S32.to(torch.complex128)
+            return self._S64
+
+    def measure(inp, prec: str, steps: int, warmup: int, stride: int):
+        grid, Sn, n_seg = inp.grid, inp.Sn, inp.n_seg
+        bank = mf.spa_bank(grid, inp.mc, inp.eta, Sn, prec)
+        st = inp.stilde(prec)
         ws = torch.empty(mf.filter_workspace_bytes(grid, prec, bank.n_tmpl, n_seg), dtype=torch.uint8, device=dev)
         peaks = torch.empty(2 * bank.n_tmpl * n_seg, dtype=torch.float64, device=dev)
         for _ in range(warmup):
@@ -184,25 +218,29 @@ def run_gpu(args):
         L.check(lib.mf_timing_read(C.byref(ms), C.byref(nl), C.byref(u1), C.byref(u2)))
         lib.mf_timing_enable(0)
         b = 16 if prec == "fp64" else 8
-        n_act = (bank.k_hi.astype(np.int64) - k_lo + 1)
+        n = inp.wl.n
+        n_act = (bank.k_hi.astype(np.int64) - grid.k_lo + 1)
         # per-unit algorithmic bytes (averaged over the workload's units):
         #   pass 1 reads the weights over the band and writes the intermediate,
         #   pass 2 reads the intermediate and writes a 16-byte peak record
-        pass1_unit = float(np.mean(b * n_act + b * wl.n))
-        pass2_unit = float(b * wl.n + 16)
+        pass1_unit = float(np.mean(b * n_act + b * n))
+        pass2_unit = float(b * n + 16)
         out = {"prec": prec, "ms_per_step": 1e3 * wall / steps, "steps": steps, "plan": mf.filter_plan(grid, prec),
                "units": bank.n_tmpl * n_seg, "peaks": res,
                "kern": {"ms": ms.value, "launches": nl.value, "u1": u1.value, "u2": u2.value,
                         "bytes": u1.value * pass1_unit + u2.value * pass2_unit},
-               "b_alg_unit": float(np.mean(b * n_act + 2 * b * wl.n + 16))}
+               "b_alg_unit": float(np.mean(b * n_act + 2 * b * n + 16)),
+               "mean_active_bins": float(np.mean(n_act))}
+        del ws
         return out
 
-    def measure_chisq(prec: str, steps: int, warmup: int, stride: int, p_bands: int):
+    def measure_chisq(inp, prec: str, steps: int, warmup: int, stride: int, p_bands: int):
         """Band mode: the filter plus chi^2 (Eq. (5)) at every sample of every unit."""
         import ctypes as C
-        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        grid, Sn, n_seg = inp.grid, inp.Sn, inp.n_seg
+        bank = mf.spa_bank(grid, inp.mc, inp.eta, Sn, prec)
         _, P = mf.psd(grid, prefix=True, device=dev)
-        st = S64 if prec == "fp64" else S32
+        st = inp.stilde(prec)
         ws = torch.empty(mf.filter_chisq_workspace_bytes(grid, prec, bank.n_tmpl, n_seg, p_bands),
                          dtype=torch.uint8, device=dev)
         for _ in range(warmup):
@@ -227,11 +265,12 @@ def run_gpu(args):
                 "pass1": {"ms": ms[0], "launches": nl[0], "units": u1[0]},
                 "chisq_at_peaks_median": float(np.median(chi))}
 
-    def measure_events(prec: str, steps: int, threshold: float, log2w: int, p_bands: int):
+    def measure_events(inp, prec: str, steps: int, threshold: float, log2w: int, p_bands: int):
         """Events path: filter + clustering, then chi^2 at the segment events."""
-        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        grid, Sn, n_seg = inp.grid, inp.Sn, inp.n_seg
+        bank = mf.spa_bank(grid, inp.mc, inp.eta, Sn, prec)
         _, P = mf.psd(grid, prefix=True, device=dev)
-        st = S64 if prec == "fp64" else S32
+        st = inp.stilde(prec)
         ws = torch.empty(mf.filter_events_workspace_bytes(grid, prec, bank.n_tmpl, n_seg, log2w), dtype=torch.uint8,
                          device=dev)
 
@@ -255,15 +294,16 @@ def run_gpu(args):
                 for s_ in range(t.shape[0]) for w in range(t.shape[1]) if t[s_, w] >= 0}
         return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl * n_seg, "events": recs}
 
-    def measure_n4m(prec: str, steps: int):
+    def measure_n4m(inp, prec: str, steps: int):
         """The filter on 4 x 2^20-sample segments (1024 s at 4096 Hz), same bank."""
+        wl = inp.wl
         g4 = mf.Grid(wl.n * 4, wl.fs, wl.f_low)
         Sn4 = mf.psd(g4, device=dev)
         S4h = Sn4.cpu().numpy()
-        s4 = synth.coloured_noise(S4h[g4.k_lo: g4.n // 2], g4.df, g4.k_lo, g4.n // 2 + 1, synth.rngs(cfg, 1)[0],
-                                  dtype=np.complex64 if prec != "fp64" else np.complex128)
+        s4 = synth.coloured_noise(S4h[g4.k_lo: g4.n // 2], g4.df, g4.k_lo, g4.n // 2 + 1,
+                                  synth.rngs(inp.cfg, 1)[0], dtype=np.complex64 if prec != "fp64" else np.complex128)
         st4 = torch.from_numpy(s4[None]).to(dev)
-        bank = mf.spa_bank(g4, mc, eta, Sn4, prec)
+        bank = mf.spa_bank(g4, inp.mc, inp.eta, Sn4, prec)
         ws = torch.empty(mf.filter_workspace_bytes(g4, prec, bank.n_tmpl, 1), dtype=torch.uint8, device=dev)
         peaks = torch.empty(2 * bank.n_tmpl, dtype=torch.float64, device=dev)
         for _ in range(3):  # warm-up steps
@@ -279,13 +319,19 @@ def run_gpu(args):
         return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl, "n": g4.n,
                 "plan": mf.filter_plan(g4, prec)}
 
-    def measure_graph(prec: str, steps: int):
-        """The same step captured once in a HIP graph and replayed; peaks checked against eager."""
-        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
-        st = S64 if prec == "fp64" else S32
+    def measure_graph(inp, prec: str, replays: int):
+        """The step captured once in a HIP graph and replayed.  Replays and eager steps
+        alternate (so both see the same clock), each timed with an event pair on the
+        stream it runs on; medians are reported, and every replay's peaks are checked
+        against the eager result."""
+        grid, Sn, n_seg = inp.grid, inp.Sn, inp.n_seg
+        bank = mf.spa_bank(grid, inp.mc, inp.eta, Sn, prec)
+        st = inp.stilde(prec)
         ws = torch.empty(mf.filter_workspace_bytes(grid, prec, bank.n_tmpl, n_seg), dtype=torch.uint8, device=dev)
         peaks = torch.empty(2 * bank.n_tmpl * n_seg, dtype=torch.float64, device=dev)
-        eager = mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)["raw"].clone()
+        eager_peaks = torch.empty_like(peaks)
+        mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=eager_peaks)
+        ref = eager_peaks.clone()
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):  # warm-up off the capture stream
@@ -295,51 +341,75 @@ def run_gpu(args):
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=peaks)
-        graph.replay()
         torch.cuda.synchronize()
-        same = bool(torch.equal(peaks, eager))
-        # warm-up replays, as the eager leg has warm-up steps: the clock ramps
-        # back up after the host-side capture
-        for _ in range(3):
+        same = True
+        for _ in range(3):  # warm-up replays and steps
             graph.replay()
+            mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=eager_peaks)
         torch.cuda.synchronize()
+        t_graph, t_eager = [], []
         with quiet_gc():
-            t0 = time.perf_counter()
-            for _ in range(steps):
+            for _ in range(replays):
+                peaks.fill_(-1.0)
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record()
                 graph.replay()
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-        same = same and bool(torch.equal(peaks, eager))
-        del graph
-        return {"ms_per_step": 1e3 * wall / steps, "steps": steps, "units": bank.n_tmpl * n_seg,
-                "peaks_equal_eager": same}
+                e1.record()
+                mf.filter(grid, bank, st, Sn, prec, workspace=ws, peaks=eager_peaks)
+                e2.record()
+                e2.synchronize()
+                t_graph.append(e0.elapsed_time(e1))
+                t_eager.append(e1.elapsed_time(e2))
+                same = same and bool(torch.equal(peaks, ref)) and bool(torch.equal(eager_peaks, ref))
+        del graph, ws
+        return {"units": bank.n_tmpl * n_seg, "replays": replays, "peaks_equal_eager": same,
+                "graph_ms_median": float(np.median(t_graph)), "eager_ms_median": float(np.median(t_eager)),
+                "graph_ms": [round(x, 4) for x in t_graph], "eager_ms": [round(x, 4) for x in t_eager]}
 
+    main_inp = Inputs(args.workload)
     tuned = None
     if args.tune:
         # time every built plan on this workload and install the fastest (untimed)
         from paper_0906_4175_amd import tune
-        tb = mf.spa_bank(grid, mc, eta, Sn, args.precision)
-        r = tune.tune(grid, tb, S64 if args.precision == "fp64" else S32, Sn, args.precision, units=(256, 512, 1024),
-                      steps=2, warmup=1, install=True)
+        tb = mf.spa_bank(main_inp.grid, main_inp.mc, main_inp.eta, main_inp.Sn, args.precision)
+        r = tune.tune(main_inp.grid, tb, main_inp.stilde(args.precision), main_inp.Sn, args.precision,
+                      units=(256, 512, 1024), steps=2, warmup=1, install=True)
         tuned = {"plan": r["best"], "ms": round(r["best_ms"], 4), "candidates": len(r["table"])}
         del tb
-    main = measure(args.precision, args.steps, args.warmup, args.timing_stride)
+    print(f"[bench] main leg: {args.steps} steps", file=sys.stderr, flush=True)
+    main = measure(main_inp, args.precision, args.steps, args.warmup, args.timing_stride)
     main["tuned"] = tuned
-    graph = measure_graph(args.precision, args.graph_steps) if args.graph_steps > 0 else None
+    graph = None
+    if args.graph_replays > 0:
+        print("[bench] graph leg", file=sys.stderr, flush=True)
+        graph = measure_graph(main_inp, args.precision, args.graph_replays)
     fp64 = None
     if args.fp64_steps > 0:
-        fp64 = measure("fp64", args.fp64_steps, 3, args.timing_stride)
+        print("[bench] fp64 leg", file=sys.stderr, flush=True)
+        fp64 = measure(main_inp, "fp64", args.fp64_steps, 2, args.timing_stride)
+    main_inp.__dict__.pop("_S64", None)
+    # legs on the single-segment workload (1024 templates x one 2^20 segment)
+    seg_inp = main_inp if args.workload == 2 else Inputs(2)
+    single = None
+    if args.workload != 2 and args.single_steps > 0:
+        print("[bench] single-segment leg", file=sys.stderr, flush=True)
+        single = measure(seg_inp, args.precision, args.single_steps, 3, args.timing_stride)
     chisq = None
     if args.chisq_steps > 0:
-        chisq = measure_chisq(args.precision, args.chisq_steps, 2, args.timing_stride, args.chisq_bands)
+        print("[bench] chi^2 leg", file=sys.stderr, flush=True)
+        chisq = measure_chisq(seg_inp, args.precision, args.chisq_steps, 2, args.timing_stride, args.chisq_bands)
     events = None
     if args.events_steps > 0:
-        e32 = measure_events(args.precision, args.events_steps, args.events_threshold, args.events_log2w,
+        print("[bench] events leg", file=sys.stderr, flush=True)
+        e32 = measure_events(seg_inp, args.precision, args.events_steps, args.events_threshold, args.events_log2w,
                              args.chisq_bands)
-        e64 = measure_events("fp64", 1, args.events_threshold, args.events_log2w, args.chisq_bands)
+        e64 = measure_events(seg_inp, "fp64", 1, args.events_threshold, args.events_log2w, args.chisq_bands)
         events = (e32, e64)
-    n4m = measure_n4m(args.precision, args.n4m_steps) if args.n4m_steps > 0 else None
-    return main, fp64, chisq, events, n4m, graph
+    n4m = None
+    if args.n4m_steps > 0:
+        print("[bench] 4M-point leg", file=sys.stderr, flush=True)
+        n4m = measure_n4m(seg_inp, args.precision, args.n4m_steps)
+    return main, fp64, chisq, events, n4m, graph, single, seg_inp.wl
 
 
 def run_refine(args):
@@ -488,11 +558,13 @@ def chisq_roofline(c, wl, khash: str):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=5)
     ap.add_argument("--precision", default="fp32_ph64", choices=["fp32_ph64", "fp32", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--single-steps", type=int, default=30,
+                    help="steps of the single-segment (1024-template) leg when the main workload is another")
     ap.add_argument("--timing-stride", type=int, default=1)  # 1: every transform launch is timed
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-procs", type=int, default=16)
@@ -504,7 +576,7 @@ def main():
     ap.add_argument("--events-threshold", type=float, default=4.0)
     ap.add_argument("--events-log2w", type=int, default=11)
     ap.add_argument("--n4m-steps", type=int, default=3)
-    ap.add_argument("--graph-steps", type=int, default=10)
+    ap.add_argument("--graph-replays", type=int, default=10)
     ap.add_argument("--tune", action="store_true", help="autotune the launch plan on the workload first")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -523,7 +595,7 @@ def main():
         print(f"[bench] cpu baseline {cpu['value']:.2f} {UNIT} on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     print(f"[bench] gpu workload {wl.name} precision {args.precision}", file=sys.stderr, flush=True)
-    m, fp64, chisq, events, n4m, graph = run_gpu(args)
+    m, fp64, chisq, events, n4m, graph, single, seg_wl = run_gpu(args)
     khash = kernel_hash()
     value = m["units"] / (m["ms_per_step"] * 1e-3)
     eff_gbs = m["b_alg_unit"] * m["units"] / (m["ms_per_step"] * 1e-3) / 1e9
@@ -535,7 +607,7 @@ def main():
         "config": {"workload": wl.name, "n": wl.n, "fs": wl.fs, "f_low": wl.f_low,
                    "n_tmpl": m["units"] // wl.n_seg, "n_seg": wl.n_seg, "precision": args.precision,
                    "phase_dtype": "f64" if args.precision != "fp32" else "f32", "sigma_dtype": "f64",
-                   "plan": m["plan"]},
+                   "mean_active_bins": round(m["mean_active_bins"]), "plan": m["plan"]},
         "effective_hbm": {"achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(eff_gbs / HBM_PEAK_GBS, 4),
                           "b_alg_per_unit": round(m["b_alg_unit"])},
@@ -551,16 +623,24 @@ def main():
                              "steps": fp64["steps"], "effective_hbm_frac": round(e64 / HBM_PEAK_GBS, 4),
                              "roofline": roofline(fp64, wl.name, khash),
                              "speedup_fp32_over_fp64": round(value / v64, 3)}
+    if single is not None:
+        vs = single["units"] / (single["ms_per_step"] * 1e-3)
+        es = single["b_alg_unit"] * single["units"] / (single["ms_per_step"] * 1e-3) / 1e9
+        line["single_segment_path"] = {
+            "workload": seg_wl.name, "value": round(vs, 1), "unit": UNIT,
+            "ms_per_step": round(single["ms_per_step"], 4), "steps": single["steps"],
+            "effective_hbm_frac": round(es / HBM_PEAK_GBS, 4), "roofline": roofline(single, seg_wl.name, khash)}
     if chisq is not None:
         vc = chisq["units"] / (chisq["ms_per_step"] * 1e-3)
+        vs_ref = vs if single is not None else value
         line["chisq_path"] = {
-            "value": round(vc, 1), "unit": UNIT, "p_bands": chisq["p_bands"],
+            "workload": seg_wl.name, "value": round(vc, 1), "unit": UNIT, "p_bands": chisq["p_bands"],
             "ms_per_step": round(chisq["ms_per_step"], 4), "steps": chisq["steps"],
             "us_per_unit": round(chisq["ms_per_step"] * 1e3 / chisq["units"], 3),
-            "slowdown_vs_filter": round(value / vc, 3),
+            "slowdown_vs_filter": round(vs_ref / vc, 3),
             "chisq_at_peaks_median": round(chisq["chisq_at_peaks_median"], 3),
             "plan": chisq["plan"],
-            "roofline": chisq_roofline(chisq, wl, khash)}
+            "roofline": chisq_roofline(chisq, seg_wl, khash)}
     if events is not None:
         e32, e64 = events
         a, b = e32["events"], e64["events"]
@@ -568,7 +648,7 @@ def main():
         drho = np.array([abs(a[k][2] / b[k][2] - 1.0) for k in both]) if both else np.zeros(0)
         dchi = np.array([abs(a[k][3] / b[k][3] - 1.0) for k in both if b[k][3] != 0.0]) if both else np.zeros(0)
         line["events_path"] = {
-            "value": round(e32["units"] / (e32["ms_per_step"] * 1e-3), 1), "unit": UNIT,
+            "workload": seg_wl.name, "value": round(e32["units"] / (e32["ms_per_step"] * 1e-3), 1), "unit": UNIT,
             "ms_per_step": round(e32["ms_per_step"], 4), "steps": e32["steps"],
             "threshold": args.events_threshold, "window_samples": 1 << args.events_log2w,
             "events": len(a), "chisq_p_bands": args.chisq_bands,
@@ -578,14 +658,20 @@ def main():
                                  "rho_max_rel_err": float(drho.max()) if both else None,
                                  "chisq_max_rel_err": float(dchi.max()) if dchi.size else None}}
     if graph is not None:
-        line["graph_path"] = {"value": round(graph["units"] / (graph["ms_per_step"] * 1e-3), 1), "unit": UNIT,
-                              "ms_per_step": round(graph["ms_per_step"], 4), "steps": graph["steps"],
-                              "peaks_equal_eager": graph["peaks_equal_eager"]}
+        line["graph_path"] = {"value": round(graph["units"] / (graph["graph_ms_median"] * 1e-3), 1), "unit": UNIT,
+                              "ms_per_replay_median": round(graph["graph_ms_median"], 4),
+                              "eager_ms_per_step_median": round(graph["eager_ms_median"], 4),
+                              "graph_over_eager": round(graph["eager_ms_median"] / graph["graph_ms_median"], 4),
+                              "replays": graph["replays"], "peaks_equal_eager": graph["peaks_equal_eager"],
+                              "replay_ms": graph["graph_ms"], "eager_ms": graph["eager_ms"]}
     if n4m is not None:
         v4 = n4m["units"] / (n4m["ms_per_step"] * 1e-3)
-        line["n4m_path"] = {"value": round(v4, 1), "unit": UNIT, "n": n4m["n"], "ms_per_step": round(n4m["ms_per_step"], 4),
+        v_ref = vs if single is not None else value
+        line["n4m_path"] = {"workload": "single-seg bank on one 4x2^20 segment", "value": round(v4, 1), "unit": UNIT,
+                            "n": n4m["n"], "ms_per_step": round(n4m["ms_per_step"], 4),
                             "steps": n4m["steps"], "samples_per_s": round(v4 * n4m["n"], 1),
-                            "samples_per_s_vs_2e20": round(v4 * n4m["n"] / (value * wl.n), 4), "plan": n4m["plan"]}
+                            "samples_per_s_vs_2e20": round(v4 * n4m["n"] / (v_ref * seg_wl.n), 4),
+                            "plan": n4m["plan"]}
     print(json.dumps(line), flush=True)
 
 

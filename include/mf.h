@@ -131,9 +131,10 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
                                  int64_t n_tmpl, int64_t n_seg);
 
 /*
- * The launch plan mf_filter uses for this grid and precision (after any
- * tuning): plan[0..7] = {N1, N2, columns per pass-1 work-group, rows per
- * pass-2 work-group, pass-1 threads, pass-2 threads, units per batch, flags}.
+ * The launch plan mf_filter uses for this grid and precision (the built-in
+ * default, or the plan installed by mf_set_plan): plan[0..7] = {N1, N2,
+ * columns per pass-1 work-group, rows per pass-2 work-group, pass-1 threads,
+ * pass-2 threads, units per batch, flags}.
  * flags bit 0: pass 1 of batch b and pass 2 of batch b-1 share a launch;
  * bit 1: the pass-2 stages exchange real and imaginary parts one after the
  * other through half the LDS (more work-groups per CU).
@@ -330,6 +331,19 @@ size_t mf_filter_chisq_workspace_bytes(const mf_grid* grid, mf_precision prec, i
 mf_status mf_filter_chisq_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 
 /*
+ * mf_set_band_plan -- installs a launch plan for mf_filter_chisq (tuning
+ * support, host state only, thread-safe) for every later call with this N
+ * and precision class (FP64 vs FP32 modes) in the process; NULL restores the
+ * built-in default.  Layout of mf_filter_plan: plan[4] and plan[5] are the
+ * pass-1 and pass-2 threads (plan[5] = B N2 / 16 selects radix-16 row stages,
+ * B N2 / 8 radix 8, where built), plan[6] the units per batch in [1, 4096],
+ * plan[7] must be 0.  The workspace size follows the installed plan.
+ * Errors: MF_E_ARG (flags, units), MF_E_SHAPE, MF_E_UNSUPPORTED (shape not
+ * built for this N and precision).
+ */
+mf_status mf_set_band_plan(const mf_grid* grid, mf_precision prec, const int32_t plan[8]);
+
+/*
  * mf_filter_chisq -- the matched filter of mf_filter with the chi^2
  * time-frequency veto of Eq. (5) (Sec. 1.2) evaluated at EVERY time sample
  * (hot call: asynchronous, no allocation, no synchronisation).  The
@@ -368,8 +382,14 @@ mf_status mf_filter_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_t
  *   bank_dev, stilde_dev, Sn_dev as for mf_filter; prefix_dev is the prefix
  *   array written by mf_psd; peaks_dev [n_tmpl][n_seg] from mf_filter.
  *   chisq_dev [n_tmpl][n_seg] double, written (NaN for an invalid peak index).
- *   rho_dev   nullable [n_tmpl][n_seg] double: |z(j)|/sigma recomputed in FP64.
+ *   rho_dev   nullable [n_tmpl][n_seg] double: |z(j)|/sigma at the same sample.
  *   2 <= p_bands <= 64.
+ * Arithmetic: the SPA phase (plus the exactly reduced time shift j k / N) and
+ * every band sum are FP64.  For MF_FP64 data the weight 4 df f^(-7/6) / S_n
+ * and the rotor are FP64; for the FP32 modes they are FP32 (hardware square
+ * root, reciprocal and sine/cosine of the reduced phase, as in mf_filter's
+ * pass 1), which bounds chi^2 and rho at about 1e-6 relative to the FP64
+ * evaluation.
  * Errors: MF_E_ARG, MF_E_SHAPE, MF_E_BAND, MF_E_HIP.
  */
 mf_status mf_chisq(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev, int64_t n_seg,

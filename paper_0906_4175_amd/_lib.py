@@ -50,7 +50,7 @@ EXPORTS = [
     "mf_template_metric", "mf_chisq", "mf_filter_chisq", "mf_filter_chisq_workspace_bytes",
     "mf_psd_prefix", "mf_rfft", "mf_rfft_workspace_bytes",
     "mf_filter_events", "mf_filter_events_workspace_bytes", "mf_chisq_events", "mf_timing_read_split",
-    "mf_filter_chisq_plan",
+    "mf_filter_chisq_plan", "mf_set_band_plan",
 ]
 
 _lib = None
@@ -101,6 +101,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_plan_candidates.argtypes = [P(MfGrid), C.c_int, P(i32), i32]
     lib.mf_set_plan.restype = C.c_int
     lib.mf_set_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
+    lib.mf_set_band_plan.restype = C.c_int
+    lib.mf_set_band_plan.argtypes = [P(MfGrid), C.c_int, P(i32)]
     lib.mf_chisq.restype = C.c_int
     lib.mf_chisq.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, vp, C.c_int, i32, vp, vp, vp, vp]
     lib.mf_filter_chisq_workspace_bytes.restype = sz

@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(64) k_finalize_band(const PartialChi* part, in
 // ---------------------------------------------------------------------------
 // One shape per N and precision (the default shape of the plain filter), the
 // first entry for each being the default; R2 is the largest pass-2 stage
-// radix (MF_BAND_R2=8 selects an R2 = 8 entry where one is built).
+// radix (an R2 = 8 entry can be installed with mf_set_band_plan).
 #define MF_BAND_SHAPES(X)                                                                                   \
     X(float, 32, 32, 16, 32, 16) X(float, 32, 64, 16, 32, 16) X(float, 64, 64, 16, 64, 16) X(float, 64, 128, 16, 32, 16)    \
     X(float, 128, 128, 16, 32, 16) X(float, 128, 256, 16, 16, 16) X(float, 256, 256, 16, 16, 16)                         \
@@ -446,16 +446,13 @@ static constexpr int band_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024
 
 static bool band_want(mf_precision prec, bool f64) { return (prec == MF_FP64) == f64; }
 
-Plan band_plan(int log2n, mf_precision prec) {
+Plan default_band_plan(int log2n, mf_precision prec) {
     Plan p{};
     p.log2n = -1;
     bool found = false;
-    int want_r2 = 16;
-    if (const char* e = getenv("MF_BAND_R2")) want_r2 = atoi(e) == 8 ? 8 : 16;
-    for (int attempt = 0; attempt < 2 && !found; ++attempt, want_r2 = 16) {
 #define MF_BFIRST(T, N1, N2, C, B, R2)                                                                      \
     if (!found && band_want(prec, std::is_same<T, double>::value) && ilog2((long long)N1 * N2) == log2n &&  \
-        R2 == want_r2) {                                                                                    \
+        R2 == 16) {                                                                                         \
         p.n1 = N1;                                                                                          \
         p.n2 = N2;                                                                                          \
         p.c1 = C;                                                                                           \
@@ -466,7 +463,6 @@ Plan band_plan(int log2n, mf_precision prec) {
         found = true;                                                                                       \
     }
     MF_BAND_SHAPES(MF_BFIRST)
-    }
 #undef MF_BFIRST
     if (!found) return p;
     // About 192 MiB of product and intermediate per batch, so that pass 2
@@ -474,14 +470,20 @@ Plan band_plan(int log2n, mf_precision prec) {
     // 2^20 FP32: 12 units 30.3k, 16 units 31.3k, 21 units 29.7k, 32 units 28.2k
     // units/s).
     const size_t bytes_per_unit = ((size_t)3 << log2n) / 2 * cx_bytes(prec);
-    size_t u = ((size_t)192 << 20) / bytes_per_unit;
-    if (const char* e = getenv("MF_BAND_UNITS")) {
-        const long v = strtol(e, nullptr, 10);
-        if (v >= 1 && v <= 4096) u = (size_t)v;
-    }
+    const size_t u = ((size_t)192 << 20) / bytes_per_unit;
     p.units = (int)(u < 1 ? 1 : (u > 4096 ? 4096 : u));
     p.fused = false;
     return p;
+}
+
+bool band_plan_supported(const Plan& q, mf_precision prec) {
+#define MF_BMATCH(T, N1, N2, C, B, R2)                                                                         \
+    if (band_want(prec, std::is_same<T, double>::value) && q.n1 == N1 && q.n2 == N2 && q.c1 == C &&          \
+        q.b2 == B && q.nt1 == band_threads(C * N1 / 16) && q.nt2 == band_threads(B * N2 / R2))               \
+        return true;
+    MF_BAND_SHAPES(MF_BMATCH)
+#undef MF_BMATCH
+    return false;
 }
 
 static size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -160,31 +160,17 @@ Plan select_plan(int log2n, mf_precision prec) {
         auto it = g_plans.find({log2n, prec == MF_FP64});
         if (it != g_plans.end()) p = it->second;
     }
-    if (const char* e = getenv("MF_PLAN")) {
-        Plan q = p;
-        int n1 = 0, n2 = 0, c1 = 0, b2 = 0, r2 = 16, xs = 0;
-        const int got = sscanf(e, "%d,%d,%d,%d,%d,%d", &n1, &n2, &c1, &b2, &r2, &xs);
-        if (got >= 4 && (int64_t)n1 * n2 == (int64_t(1) << log2n) && (r2 == 8 || r2 == 16)) {
-            q.n1 = n1;
-            q.n2 = n2;
-            q.c1 = c1;
-            q.b2 = b2;
-            q.nt1 = c1 * n1 / 16 < 64 ? 64 : (c1 * n1 / 16 > 1024 ? 1024 : c1 * n1 / 16);
-            q.nt2 = b2 * n2 / r2 < 64 ? 64 : (b2 * n2 / r2 > 1024 ? 1024 : b2 * n2 / r2);
-            q.fused = false;
-            q.split = xs != 0;
-            if (plan_supported(q, prec)) p = q;
-        }
-    }
-    if (const char* e = getenv("MF_FUSED")) {
-        const int b16 = p.b2 * p.n2 / 16;
-        const int nt16 = b16 < 64 ? 64 : (b16 > 1024 ? 1024 : b16);
-        p.fused = e[0] == '1' && p.nt1 == p.nt2 && p.nt2 == nt16;
-    }
-    if (const char* e = getenv("MF_UNITS")) {
-        const long v = strtol(e, nullptr, 10);
-        if (v >= 1 && v <= 4096) p.units = (int)v;
-    }
+    return p;
+}
+
+// Band-mode plans installed by mf_set_band_plan, keyed like g_plans.
+std::map<std::pair<int, bool>, Plan> g_band_plans;
+
+Plan band_plan(int log2n, mf_precision prec) {
+    Plan p = default_band_plan(log2n, prec);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_band_plans.find({log2n, prec == MF_FP64});
+    if (it != g_band_plans.end()) p = it->second;
     return p;
 }
 
@@ -270,6 +256,34 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     if (q.fused && (q.nt1 != q.nt2 || q.nt2 != nt16))
         return fail(MF_E_UNSUPPORTED, "pipelined step needs equal work-group sizes and radix-16 row stages");
     mf::g_plans[{l, prec == MF_FP64}] = q;
+    return ok();
+}
+
+mf_status mf_set_band_plan(const mf_grid* grid, mf_precision prec, const int32_t plan[8]) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    std::lock_guard<std::mutex> lk(mf::g_plan_mu);
+    if (!plan) {
+        mf::g_band_plans.erase({l, prec == MF_FP64});
+        return ok();
+    }
+    mf::Plan q = mf::default_band_plan(l, prec);
+    if (q.log2n != l) return fail(MF_E_UNSUPPORTED, "no band-mode plan for n=%lld", (long long)grid->n);
+    q.n1 = plan[0];
+    q.n2 = plan[1];
+    q.c1 = plan[2];
+    q.b2 = plan[3];
+    q.nt1 = plan[4];
+    q.nt2 = plan[5];
+    q.units = plan[6];
+    if (plan[7] != 0) return fail(MF_E_ARG, "band-mode plan flags %d: must be 0", plan[7]);
+    if ((int64_t)q.n1 * q.n2 != grid->n || !mf::band_plan_supported(q, prec))
+        return fail(MF_E_UNSUPPORTED, "band-mode plan %dx%d c=%d b=%d (threads %d/%d) is not built for this N/precision",
+                    q.n1, q.n2, q.c1, q.b2, q.nt1, q.nt2);
+    if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
+    mf::g_band_plans[{l, prec == MF_FP64}] = q;
     return ok();
 }
 

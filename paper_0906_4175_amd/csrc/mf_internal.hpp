@@ -33,9 +33,7 @@ Plan default_plan(int log2n, mf_precision prec);
 bool plan_supported(const Plan& p, mf_precision prec);
 // instantiated shapes for this N and precision (units = 0); returns the count
 int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap);
-// default plan, overridden by MF_PLAN="n1,n2,c1,b2[,r2[,xs]]" (r2: largest
-// pass-2 radix, 16 or 8; xs: 1 for the split pass-2 exchange) and
-// MF_UNITS="units" when set
+// the default plan, or the one installed by mf_set_plan
 Plan select_plan(int log2n, mf_precision prec);
 
 size_t cx_bytes(mf_precision prec);
@@ -89,8 +87,10 @@ struct BandLayout {
     size_t off_w, off_tab, off_q, off_inter, off_part, total;
     int64_t units_per_batch;
 };
-// the band-mode shape for this N and precision (log2n = -1 if none); units from
-// MF_BAND_UNITS when set
+// the built-in band-mode shape for this N and precision (log2n = -1 if none)
+Plan default_band_plan(int log2n, mf_precision prec);
+bool band_plan_supported(const Plan& p, mf_precision prec);
+// the default band-mode plan, or the one installed by mf_set_band_plan
 Plan band_plan(int log2n, mf_precision prec);
 BandLayout band_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg, int p_bands);
 

@@ -26,13 +26,15 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f)
-                  for f in ("k_filter.hip", "k_filter_chisq.hip", "filter_tiles.hpp", "mf_device.hpp")]
+# every device source: a profile goes stale when any kernel's code changes
+KERNEL_SOURCES = sorted(os.path.join(ROOT, "paper_0906_4175_amd", "csrc", f)
+                        for f in os.listdir(os.path.join(ROOT, "paper_0906_4175_amd", "csrc"))
+                        if f.endswith((".hip", ".hpp")))
 
 
 def kernel_hash() -> str:
-    """Hash of the transform kernels' code: comments and whitespace are left out,
-    so a profile stays valid across edits that change neither."""
+    """Hash of the device code (every .hip and .hpp source): comments and whitespace
+    are left out, so a profile stays valid across edits that change neither."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, encoding="utf-8") as fh:

@@ -54,6 +54,25 @@ def set_plan(n: int, prec: int, plan: dict | None) -> None:
     L.check(lib.mf_set_plan(C.byref(g), prec, arr))
 
 
+def set_band_plan(n: int, prec: int, plan: dict | None) -> None:
+    """Install a plan for the chi^2 band mode (mf_set_band_plan); None restores the default."""
+    lib = L.load()
+    g = _canonical_grid(n)
+    if plan is None:
+        L.check(lib.mf_set_band_plan(C.byref(g), prec, None))
+        return
+    arr = (C.c_int32 * 8)(*[int(plan[k]) for k in PLAN_KEYS])
+    L.check(lib.mf_set_band_plan(C.byref(g), prec, arr))
+
+
+def current_band_plan(n: int, prec: int) -> dict:
+    lib = L.load()
+    g = _canonical_grid(n)
+    arr = (C.c_int32 * 8)()
+    L.check(lib.mf_filter_chisq_plan(C.byref(g), prec, arr))
+    return dict(zip(PLAN_KEYS, [int(x) for x in arr]))
+
+
 def current_plan(n: int, prec: int) -> dict:
     lib = L.load()
     g = _canonical_grid(n)

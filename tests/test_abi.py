@@ -244,6 +244,43 @@ def test_chisq_entry_points_validation(lib):
     assert b"chisq_series" in lib.mf_last_error()
 
 
+def test_set_band_plan_validation(lib):
+    """The band mode's launch plan is set only through mf_set_band_plan (no hidden switches)."""
+    g = _grid()
+    out = (C.c_int32 * 8)()
+    assert lib.mf_set_band_plan(C.byref(g), 1, None) == 0
+    assert lib.mf_filter_chisq_plan(C.byref(g), 1, out) == 0
+    default = list(out)
+    assert default[:6] == [256, 4096, 16, 1, 256, 256] and default[6] == 16 and default[7] == 0
+    w_default = int(lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 64, 1, 16))
+    r8 = (C.c_int32 * 8)(*(default[:5] + [512, 5, 0]))  # radix-8 rows, 5 units per batch
+    assert lib.mf_set_band_plan(C.byref(g), 1, r8) == 0
+    assert lib.mf_filter_chisq_plan(C.byref(g), 1, out) == 0
+    assert list(out)[5:7] == [512, 5]
+    # the workspace follows the installed batch
+    assert int(lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 64, 1, 16)) < w_default
+    bad = (C.c_int32 * 8)(*(default[:5] + [384, 5, 0]))  # no such row radix
+    assert lib.mf_set_band_plan(C.byref(g), 1, bad) == -6
+    bad = (C.c_int32 * 8)(*(default[:6] + [0, 0]))  # units 0
+    assert lib.mf_set_band_plan(C.byref(g), 1, bad) == -1
+    bad = (C.c_int32 * 8)(*(default[:6] + [4, 1]))  # flags must be 0
+    assert lib.mf_set_band_plan(C.byref(g), 1, bad) == -1
+    bad = (C.c_int32 * 8)(512, 512, 16, 8, 512, 256, 4, 0)  # wrong N
+    assert lib.mf_set_band_plan(C.byref(g), 1, bad) == -6
+    # the FP64 class is separate and keeps its default
+    assert lib.mf_filter_chisq_plan(C.byref(g), 0, out) == 0 and out[6] == 8
+    assert lib.mf_set_band_plan(C.byref(g), 1, None) == 0
+    assert lib.mf_filter_chisq_plan(C.byref(g), 1, out) == 0 and list(out) == default
+
+
+def test_no_environment_switches_in_the_library():
+    """Launch structure and workspace layout depend only on declared calls."""
+    csrc = os.path.join(ROOT, "paper_0906_4175_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "getenv" not in txt, f
+
+
 def test_kernel_hash_ignores_comments_and_whitespace(tmp_path, monkeypatch):
     """Profiles stay valid across comment edits and go stale on code edits."""
     from paper_0906_4175_amd import profile_summary as ps

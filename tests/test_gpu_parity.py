@@ -6,6 +6,7 @@ Tolerances (see the ρ-error metric in tests/_data.py):
                 peak rho <= 1e-4 relative, peak index exact or a near-tie
                 within 2e-4 of the oracle maximum; units with rho >= 8 exact.
 """
+import contextlib
 import math
 
 import numpy as np
@@ -329,19 +330,32 @@ def test_snr_grad_matches_oracle(mf, prec):
 # ---------------------------------------------------------------------------
 # Batching invariance: launch structure must not change results
 # ---------------------------------------------------------------------------
-def _with_env(env, fn):
-    import os
-    old = {k: os.environ.get(k) for k in env}
+def _plan(n1, n2, c, b, units, fused=False, split=False, r2=16):
+    """A launch plan in the layout of mf_filter_plan (pass-2 threads select the row radix)."""
+    def clamp(x):
+        return max(64, min(1024, x))
+    return {"n1": n1, "n2": n2, "cols_per_wg": c, "rows_per_wg": b, "threads_pass1": clamp(c * n1 // 16),
+            "threads_pass2": clamp(b * n2 // r2), "units_per_batch": units,
+            "flags": (1 if fused else 0) | (2 if split else 0)}
+
+
+@contextlib.contextmanager
+def _installed(n, prec, plan=None, band_plan=None):
+    """Install a filter and/or band-mode plan (mf_set_plan / mf_set_band_plan) for the block."""
+    from paper_0906_4175_amd import tune
+    import paper_0906_4175_amd as m
+    p = m.PRECISIONS[prec]
     try:
-        for k, v in env.items():
-            os.environ[k] = v
-        return fn()
+        if plan is not None:
+            tune.set_plan(n, p, plan)
+        if band_plan is not None:
+            tune.set_band_plan(n, p, band_plan)
+        yield
     finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+        if plan is not None:
+            tune.set_plan(n, p, None)
+        if band_plan is not None:
+            tune.set_band_plan(n, p, None)
 
 
 @pytest.mark.parametrize("prec", ["fp32_ph64", "fp64"])
@@ -357,30 +371,32 @@ def test_batching_and_fusion_bitwise_invariant(mf, prec):
     Sn = mf.psd(g)
     bank = mf.spa_bank(g, mc, eta, Sn, prec)
     st = torch.from_numpy(S).to(_dev())
-    shape = "256,4096,16,1" if prec != "fp64" else "1024,1024,4,4"  # shapes with a pipelined-step variant
+    shape = (256, 4096, 16, 1) if prec != "fp64" else (1024, 1024, 4, 4)  # shapes with a pipelined-step variant
+
+    def run(plan):
+        with _installed(n, prec, plan=plan):
+            res = mf.filter(g, bank, st, Sn, prec, threshold=5.0)
+            return {k: res[k].cpu().clone() for k in ("rho", "j", "n_above")}
     runs = {}
-    for units in ("3", "8", "64"):
-        for fused in ("1", "0"):
-            res = _with_env({"MF_PLAN": shape, "MF_UNITS": units, "MF_FUSED": fused},
-                            lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
-            runs[(units, fused)] = {k: res[k].cpu().clone() for k in ("rho", "j", "n_above")}
-    ref = runs[("8", "1")]
+    for units in (3, 8, 64):
+        for fused in (True, False):
+            runs[(units, fused)] = run(_plan(*shape, units, fused=fused))
+    ref = runs[(8, True)]
     for key, r in runs.items():
         for f in ("rho", "j", "n_above"):
             assert torch.equal(r[f], ref[f]), (key, f)
     # the split pass-2 exchange moves the same values through LDS: bitwise equal
-    xs = "256,4096,16,1,16" if prec != "fp64" else "256,4096,8,1,16"
-    split = _with_env({"MF_PLAN": xs + ",1", "MF_UNITS": "5"}, lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
-    whole = _with_env({"MF_PLAN": xs + ",0", "MF_UNITS": "64"}, lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
-    # and with the pipelined step (FP32 shape; FP64 work-group sizes differ, so it runs separate launches)
-    piped = _with_env({"MF_PLAN": xs + ",1", "MF_UNITS": "7", "MF_FUSED": "1"},
-                      lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
+    xs = (256, 4096, 16, 1) if prec != "fp64" else (256, 4096, 8, 1)
+    split = run(_plan(*xs, 5, split=True))
+    whole = run(_plan(*xs, 64, split=False))
+    # and with the pipelined step (FP32 shape only: the FP64 shape's two passes
+    # have different work-group sizes, which the step cannot mix)
+    piped = run(_plan(*xs, 7, split=True, fused=prec != "fp64"))
     for f in ("rho", "j", "n_above"):
-        assert torch.equal(split[f].cpu(), whole[f].cpu()), f
-        assert torch.equal(piped[f].cpu(), whole[f].cpu()), f
+        assert torch.equal(split[f], whole[f]), f
+        assert torch.equal(piped[f], whole[f]), f
     if prec != "fp64":
-        other = _with_env({"MF_PLAN": "1024,1024,8,4", "MF_UNITS": "16"},
-                          lambda: mf.filter(g, bank, st, Sn, prec, threshold=5.0))
+        other = run(_plan(1024, 1024, 8, 4, 16))
         rel = (other["rho"].cpu() - ref["rho"]).abs() / ref["rho"]
         assert float(rel.max()) < 2e-5
         for i in range(2):  # injected units (rho >= 8): same sample under either split, as the oracle
@@ -593,7 +609,7 @@ def _band_bank():
 
 
 @pytest.mark.parametrize("prec,p,units", [("fp64", 16, None), ("fp32_ph64", 16, None), ("fp32_ph64", 2, None),
-                                          ("fp64", 5, "3"), ("fp32_ph64", 64, "5")])
+                                          ("fp64", 5, 3), ("fp32_ph64", 64, 5)])
 def test_filter_chisq_series_matches_oracle(mf, prec, p, units):
     """N=2^14 at 1024 Hz, 8 templates x 2 segments (one injection each): chi^2 and rho series of every unit."""
     print(f"[filter_chisq series] prec={prec} p={p} units={units}", flush=True)
@@ -610,8 +626,10 @@ def test_filter_chisq_series_matches_oracle(mf, prec, p, units):
     bank = mf.spa_bank(g, mc, eta, Sn, prec)
     st = torch.from_numpy(np.stack(segs)).to(_dev())
     n_units = len(mc) * 2
-    res = _with_env({"MF_BAND_UNITS": units} if units else {},
-                    lambda: mf.filter_chisq(g, bank, st, Sn, P, prec, p_bands=p, series_units=list(range(n_units))))
+    from paper_0906_4175_amd import tune
+    band = dict(tune.current_band_plan(n, mf.PRECISIONS[prec]), units_per_batch=units) if units else None
+    with _installed(n, prec, band_plan=band):
+        res = mf.filter_chisq(g, bank, st, Sn, P, prec, p_bands=p, series_units=list(range(n_units)))
     chi_s = res["chisq_series"].cpu().numpy().astype(np.float64)
     rho_s = res["series"].cpu().numpy().astype(np.float64)
     tol = 1e-9 if prec == "fp64" else 1e-4
@@ -952,7 +970,7 @@ def test_every_candidate_plan_matches_default(mf, prec):
 
 
 def test_band_mode_radix8_rows_match_radix16(mf):
-    """The band mode with radix-8 row stages (MF_BAND_R2=8) against the default radix 16."""
+    """The band mode with radix-8 row stages (installed with mf_set_band_plan) against the default radix 16."""
     print("[band r2]", flush=True)
     n, fs = 1 << 20, 4096.0
     inj = dict(m1=3.0, m2=1.5, snr=15.0, j0=123457, phi0=1.0)
@@ -963,10 +981,11 @@ def test_band_mode_radix8_rows_match_radix16(mf):
     bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
     st = torch.from_numpy(s[None]).to(_dev())
     a = mf.filter_chisq(g, bank, st, Sn, P, "fp32_ph64", series_units=[0, 11])
-    b = _with_env({"MF_BAND_R2": "8"}, lambda: (mf.filter_chisq_plan(g), mf.filter_chisq(
-        g, bank, st, Sn, P, "fp32_ph64", series_units=[0, 11])))
-    assert b[0]["threads_pass2"] == 512
-    b = b[1]
+    from paper_0906_4175_amd import tune
+    r8 = dict(tune.current_band_plan(n, mf.PRECISIONS["fp32_ph64"]), threads_pass2=512)
+    with _installed(n, "fp32_ph64", band_plan=r8):
+        assert mf.filter_chisq_plan(g)["threads_pass2"] == 512
+        b = mf.filter_chisq(g, bank, st, Sn, P, "fp32_ph64", series_units=[0, 11])
     assert torch.allclose(b["rho"], a["rho"], rtol=2e-5, atol=0)
     scale = a["chisq"] + a["rho"] ** 2 + 1.0
     assert float(((b["chisq"] - a["chisq"]).abs() / scale).max()) < 2e-5
