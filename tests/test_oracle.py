@@ -188,6 +188,62 @@ def test_template_amplitude_and_band():
     np.testing.assert_allclose(np.abs(h[k_lo:k_hi + 1]), f[k_lo:k_hi + 1] ** (-7.0 / 6.0), rtol=1e-14)
 
 
+def _newtonian_chirp_time(f, mc):
+    """Newtonian time to coalescence from GW frequency f (quadrupole inspiral):
+    5/256 (pi f)^(-8/3) (G M_c / c^3)^(-5/3).  Accepts complex f."""
+    return 5.0 / 256.0 * (np.pi * f) ** (-8.0 / 3.0) * (mc * 4.925490947641267e-6) ** (-5.0 / 3.0)
+
+
+@pytest.mark.parametrize("m1,m2", [(1.4, 1.4), (3.0, 1.0), (20.0, 5.0)])
+def test_spa_amplitude_from_stationary_phase_relation(m1, m2):
+    """Stationary phase: a quadrupole chirp of amplitude ~ f^(2/3) that sweeps through f
+    at the rate set by the chirp time has |h(f)|^2 proportional to f^(4/3) |d tau/df|.
+    The oracle's amplitude must make that ratio constant over the band."""
+    mc, _ = map(float, synth.mc_eta(m1, m2))
+    f = np.geomspace(40.0, 1000.0, 41)
+    h = 1e-20 * f
+    dtau = np.imag(_newtonian_chirp_time(f + 1j * h, mc)) / h  # complex-step derivative
+    ratio = O.spa_amplitude(f) ** 2 / (f ** (4.0 / 3.0) * np.abs(dtau))
+    assert np.max(np.abs(ratio / ratio[0] - 1.0)) < 1e-12
+
+
+def _time_domain_chirp_spectrum(m1, m2, fs, n, f_start, f_stop):
+    """One-sided spectrum dt * DFT of a Newtonian chirp built in the time domain:
+    frequency f(t) from inverting the chirp time, phase by summing 2 pi f dt,
+    amplitude (pi M_c f)^(2/3), with raised-cosine tapers at both ends."""
+    mc, _ = map(float, synth.mc_eta(m1, m2))
+    Mc = mc * 4.925490947641267e-6
+    tau_start = float(_newtonian_chirp_time(f_start, mc))
+    tau_stop = float(_newtonian_chirp_time(f_stop, mc))
+    dt = 1.0 / fs
+    tau = tau_start + 1.0 - np.arange(n) * dt
+    on = (tau > tau_stop) & (tau <= tau_start)
+    f = np.zeros(n)
+    f[on] = (5.0 / (256.0 * tau[on])) ** (3.0 / 8.0) * Mc ** (-5.0 / 8.0) / math.pi
+    phase = np.cumsum(2.0 * math.pi * f) * dt
+    amp = np.where(on, (math.pi * Mc * f) ** (2.0 / 3.0), 0.0)
+    w = np.ones(n)
+    i0 = int(np.argmax(on))
+    i1 = n - 1 - int(np.argmax(on[::-1]))
+    l0, l1 = int(2.0 * fs), int(0.02 * fs)
+    w[i0:i0 + l0] = 0.5 - 0.5 * np.cos(np.pi * np.arange(l0) / l0)
+    w[i1 - l1 + 1:i1 + 1] = 0.5 + 0.5 * np.cos(np.pi * np.arange(l1) / l1)
+    return np.fft.rfftfreq(n, dt), np.fft.rfft(amp * np.cos(phase) * w) * dt
+
+
+@pytest.mark.parametrize("m1,m2", [(1.4, 1.4), (3.0, 1.0)])
+def test_spa_amplitude_matches_time_domain_chirp(m1, m2):
+    """Brute force: the spectrum of a time-domain Newtonian chirp (64 s at 4096 Hz,
+    30-700 Hz) has the oracle's amplitude shape between 50 and 400 Hz: |H| / a(f)
+    is flat to about 1% and its log-log slope vanishes."""
+    fq, H = _time_domain_chirp_spectrum(m1, m2, 4096.0, 1 << 18, 30.0, 700.0)
+    sel = (fq > 50.0) & (fq < 400.0)
+    r = np.abs(H[sel]) / O.spa_amplitude(fq[sel])
+    assert r.max() / r.min() < 1.03
+    slope = np.polyfit(np.log(fq[sel]), np.log(r), 1)[0]
+    assert abs(slope) < 5e-3
+
+
 # ---------------------------------------------------------------------------
 # Quadrature pair and z = x + i y
 # ---------------------------------------------------------------------------
