@@ -44,3 +44,16 @@ def peak_index_ok(j_gpu: int, rho_series_ora: np.ndarray, j_ora: int, rel: float
     if j_gpu == j_ora:
         return True
     return bool(rho_series_ora[j_gpu] >= rho_series_ora[j_ora] * (1.0 - rel))
+
+
+def n_above_bounds(rho_series_ora: np.ndarray, threshold: float, rel: float = 1e-4) -> tuple[int, int]:
+    """Range of threshold counts consistent with a rho series within rel of the oracle's.
+
+    A GPU sample counts when rho_g >= threshold, and rho_g lies in
+    [rho_o (1 - rel), rho_o (1 + rel)]; so every sample with rho_o >= th/(1 - rel)
+    counts and none with rho_o < th/(1 + rel) does.  Only samples between the two
+    (near-ties with the threshold) may go either way.
+    """
+    lo = int(np.count_nonzero(rho_series_ora >= threshold / (1.0 - rel)))
+    hi = int(np.count_nonzero(rho_series_ora >= threshold / (1.0 + rel)))
+    return lo, hi

@@ -203,7 +203,8 @@ def test_filter_fp32_small_many_segments(mf):
             ties += int(jg != o["j"])
             if o["rho"] >= 8.0:
                 assert jg == o["j"]
-            assert abs(int(res["n_above"][t, s]) - o["n_above"]) <= 2
+            lo, hi = D.n_above_bounds(o["series"], 4.0)
+            assert lo <= int(res["n_above"][t, s]) <= hi, (t, s, lo, hi)
     print(f"  worst series error {worst:.2e}, near-tie index accepts {ties}")
     assert worst < 1e-4
 
@@ -243,7 +244,8 @@ def test_filter_full_size_sampled(mf):
 
 
 def test_filter_window_threshold_ragged_batches(mf):
-    """7 templates x 3 segments at N=2^20 (ragged last batch), search window and threshold count."""
+    """7 templates x 3 segments at N=2^20 in batches of 4 units (a ragged last batch of 1),
+    search window and threshold count."""
     print("[filter window/ragged]", flush=True)
     n, fs = 1 << 20, 4096.0
     mc, eta = synth.mc_eta([1.2, 1.5, 2.0, 3.0, 6.0, 12.0, 20.0], [1.1, 1.4, 1.9, 1.0, 5.0, 1.2, 14.0])
@@ -256,9 +258,13 @@ def test_filter_window_threshold_ragged_batches(mf):
     Sn = mf.psd(g)
     bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
     win = (1000, 900000)
-    res = mf.filter(g, bank, torch.from_numpy(S).to(_dev()), Sn, "fp32_ph64", threshold=4.5, window=win)
+    from paper_0906_4175_amd import tune
+    ragged = dict(tune.current_plan(n, mf.PRECISIONS["fp32_ph64"]), units_per_batch=4)
+    with _installed(n, "fp32_ph64", plan=ragged):
+        assert mf.filter_plan(g)["units_per_batch"] == 4  # 21 units: batches 4, 4, 4, 4, 4, 1
+        res = mf.filter(g, bank, torch.from_numpy(S).to(_dev()), Sn, "fp32_ph64", threshold=4.5, window=win)
     res2 = mf.filter(g, bank, torch.from_numpy(S).to(_dev()), Sn, "fp32_ph64", threshold=4.5, window=win)
-    # repeat runs are bitwise identical (order-independent packed-key maximum)
+    # the default single batch gives bitwise the same (order-independent packed-key maximum)
     for key in ("rho", "j", "n_above"):
         assert torch.equal(res[key], res2[key])
     for t in range(7):
@@ -268,7 +274,9 @@ def test_filter_window_threshold_ragged_batches(mf):
             assert win[0] <= jg < win[1]
             assert float(res["rho"][t, si]) == pytest.approx(o["rho"], rel=1e-4)
             assert D.peak_index_ok(jg, o["series"], o["j"])
-            assert abs(int(res["n_above"][t, si]) - o["n_above"]) <= 2
+            w = o["series"][win[0]:win[1]]
+            lo, hi = D.n_above_bounds(w, 4.5)
+            assert lo <= int(res["n_above"][t, si]) <= hi, (t, si, lo, hi)
 
 
 def test_fp32_phase_mode_runs_and_is_worse(mf):
