@@ -137,7 +137,11 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
  * pass-2 threads, units per batch, flags}.
  * flags bit 0: pass 1 of batch b and pass 2 of batch b-1 share a launch;
  * bit 1: the pass-2 stages exchange real and imaginary parts one after the
- * other through half the LDS (more work-groups per CU).
+ * other through half the LDS (more work-groups per CU); bit 2 (with bit 1):
+ * that exchange uses bank-conflict-free layouts (4096-point rows); bit 3:
+ * pass 1 skips its first column stage for templates whose band lies below
+ * row N1/16 (every such butterfly has one non-zero input).  Every plan gives
+ * bitwise the same results.
  */
 mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 

@@ -117,6 +117,12 @@ struct Pass1 {
     }
     static constexpr bool XS = NS > 1 && all_full();
     static constexpr int EPT = C * N1 / NT;
+    // Narrow bands (product rows k1 < N1/16 only: k_hi < N2 N1 / 16, templates
+    // heavier than about 17 M_sun at N1 = 256): every stage-0 butterfly has a
+    // single non-zero input, so its 16 outputs all equal that input and stage 1
+    // reads the products directly (no stage-0 transform, one LDS value per row).
+    static constexpr bool NARROW_OK = MODE == P1_PRODUCT && XS && NS == 2 && radix_at(N1, 0) == 16 &&
+                                      radix_at(N1, 1) == 16 && C * N1 / 16 == NT;
     static constexpr size_t BUF_BYTES = (size_t)N1 * C * (XS ? sizeof(T) : sizeof(cx<T>));
     static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1) * sizeof(cx<T>);
 
@@ -160,6 +166,7 @@ struct Pass1 {
             }
         }
         cx<T>* inter = (cx<T>*)a.inter + ul * N;
+        [[maybe_unused]] const bool narrow = NARROW_OK && a.prune1 != 0 && khi < (N1 / 16) * N2;
 
         static_for<0, NS>([&](auto S_) {
             constexpr int s = decltype(S_)::value;
@@ -167,6 +174,43 @@ struct Pass1 {
             constexpr int NSPAN = span_before(N1, s);
             constexpr int NBF = C * N1 / R;
             constexpr int BPT = (NBF + NT - 1) / NT;
+            if constexpr (s == 0 && NARROW_OK) {
+                if (narrow) {  // uniform over the work-group
+                    // thread (row k1 = j, column c): the product of its bin, or zero
+                    const int c = tid % C, j = tid / C;
+                    const int k = j * N2 + k2_0 + c;
+                    cx<T> x{T(0), T(0)};
+                    const cx<T> wk = w[(k >= klo && k <= khi) ? k : 0];
+                    if (k >= klo && k <= khi) {
+                        cx<T> rotor;
+                        if constexpr (PH == 0) {
+                            rotor = spa_rotor_ph64<T>(coef, (double)k);
+                        } else {
+                            rotor = spa_rotor_ph32(coef, (float)k);
+                        }
+                        x = cmul(rotor, wk);
+                    }
+                    fill_stage_twiddles<T, N1>(tw, tid, NT);
+                    constexpr T INV_M1 = (T)1 / (T)(16 * R1);
+                    for (int q = tid; q < T1; q += NT) {
+                        const int kk = q / R1, r = q % R1;
+                        t1[q] = root_of_unity((T)((kk * r) & (16 * R1 - 1)) * INV_M1);
+                    }
+                    // stage-1 input r of every butterfly of column c is the product of row r
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        __syncthreads();
+                        fbuf[j * C + c] = part ? x.y : x.x;
+                        __syncthreads();
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            if (part) carry[r].y = fbuf[r * C + c];
+                            else carry[r].x = fbuf[r * C + c];
+                        }
+                    }
+                    return;
+                }
+            }
             cx<T> v[BPT][R];
 #pragma unroll
             for (int i = 0; i < BPT; ++i) {
@@ -308,6 +352,31 @@ struct Pass1 {
 };
 
 // ---------------------------------------------------------------------------
+// Bank-conflict-free exchange layouts of a 4096-point row transformed by three
+// radix-16 stages with one butterfly (16 values) per thread.  With x = 256 h +
+// 16 m + l, a wave writes x = 16 j + r after stage 0 and 256 (j >> 4) + 16 r +
+// (j & 15) after stage 1 (r fixed per instruction, j over the lanes), and reads
+// x = j + 256 r before stages 1 and 2.  No padding serves the first write and
+// the reads together, so the first exchange stores x at x ^ m ^ ((h & 3) << 4)
+// (an XOR swizzle: l ^ m and the low bits of m ^ h differ across the 64 lanes
+// of every access); the second pads 16 slots per 256 (x + 16 h), whose offsets
+// stay immediates.  Every access touches distinct banks for 64 banks of one
+// lane each and for 32 banks per half-wave (so also for 8-byte elements).
+// The buffer needs 4336 slots.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cf_wr0(int j) {  // slot of x = 16 j; x = 16 j + r is at cf_wr0(j) ^ r
+    return (16 * j) ^ (j & 15) ^ (((j >> 4) & 3) << 4);
+}
+__device__ __forceinline__ int cf_rd0(int j, int r) {  // slot of x = j + 256 r, j < 256 (first layout)
+    return 256 * r + ((j ^ (j >> 4)) ^ ((r & 3) << 4));
+}
+__device__ __forceinline__ int cf_wr1(int j, int r) {  // slot of x = 256 (j >> 4) + 16 r + (j & 15)
+    return 272 * (j >> 4) + (j & 15) + 16 * r;
+}
+__device__ __forceinline__ int cf_rd1(int j, int r) { return j + 272 * r; }  // x = j + 256 r (second layout)
+constexpr int kCfSlots = 4336;
+
+// ---------------------------------------------------------------------------
 // Pass 2 tile: B rows j1 of one unit.
 // Row j1: z[j1 + N1 j2] = sum_k2 (Y[j1][k2] t^k2) e^{2 pi i j2 k2 / N2}, t = e^{2 pi i j1 / N}.
 // The four-step factor t^k2 is folded into the stage twiddles: writing k2 in
@@ -316,7 +385,7 @@ struct Pass1 {
 // twiddle pass is needed and the result is exact (not only up to a phase).
 // The last stage squares |z| and reduces (max |z|^2, lowest index, count).
 // ---------------------------------------------------------------------------
-template <typename T, bool RAW, int N1, int N2, int B, int NT, int MAXR = 16, bool XSPLIT = false>
+template <typename T, bool RAW, int N1, int N2, int B, int NT, int MAXR = 16, int XS = 0>
 struct Pass2 {
     static constexpr int64_t N = (int64_t)N1 * N2;
     static constexpr int NS = num_stages(N2, MAXR);
@@ -325,11 +394,16 @@ struct Pass2 {
     static constexpr int TW = tw_total(N2, MAXR);
     static constexpr bool F64 = std::is_same<T, double>::value;
     static constexpr int R0 = radix_at(N2, 0, MAXR);
-    // XSPLIT: exchange the real parts, then the imaginary parts, through a
+    // XS >= 1: exchange the real parts, then the imaginary parts, through a
     // buffer of B * PN2 scalars (half the LDS, so more work-groups per CU,
     // for two more barriers per exchange); needs the same radix at every stage.
-    static constexpr bool SPLIT = XSPLIT;
-    static_assert(!XSPLIT || (N2 == ipow_c(MAXR, NS) && NS > 1), "split exchange needs one radix at every stage");
+    // XS == 2 (4096-point rows of three radix-16 stages, one row per
+    // work-group): bank-conflict-free layouts instead of the padding (below).
+    static constexpr bool SPLIT = XS >= 1;
+    static constexpr bool CF = XS == 2;
+    static_assert(!SPLIT || (N2 == ipow_c(MAXR, NS) && NS > 1), "split exchange needs one radix at every stage");
+    static_assert(!CF || (N2 == 4096 && MAXR == 16 && B == 1 && NT == 256 && PN2 >= kCfSlots),
+                  "conflict-free layouts: 4096-point rows");
     // FP32 peak search over the full series when every thread holds exactly
     // one last-stage butterfly: each thread keeps its largest |z|^2 bits, the
     // work-group takes the maximum, and only threads that hold it look for
@@ -610,8 +684,17 @@ struct Pass2 {
                             const int b = bf / PER_ROW;
                             const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
                             T* dst = fbuf + b * PN2;
+                            if constexpr (CF && s == 0) {
+                                const int w0 = cf_wr0(j);
 #pragma unroll
-                            for (int r = 0; r < R; ++r) dst[off<NSPAN>(idxD, r)] = part ? v[i][r].y : v[i][r].x;
+                                for (int r = 0; r < R; ++r) dst[w0 ^ r] = part ? v[i][r].y : v[i][r].x;
+                            } else if constexpr (CF) {
+#pragma unroll
+                                for (int r = 0; r < R; ++r) dst[cf_wr1(j, r)] = part ? v[i][r].y : v[i][r].x;
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < R; ++r) dst[off<NSPAN>(idxD, r)] = part ? v[i][r].y : v[i][r].x;
+                            }
                         }
                     }
                     __syncthreads();
@@ -624,8 +707,16 @@ struct Pass2 {
                             const T* src = fbuf + b * PN2;
 #pragma unroll
                             for (int r = 0; r < R; ++r) {
-                                if (part) carry[i][r].y = src[off<PER_ROW>(j, r)];
-                                else carry[i][r].x = src[off<PER_ROW>(j, r)];
+                                int at;
+                                if constexpr (CF && s == 0) {
+                                    at = cf_rd0(j, r);
+                                } else if constexpr (CF) {
+                                    at = cf_rd1(j, r);
+                                } else {
+                                    at = off<PER_ROW>(j, r);
+                                }
+                                if (part) carry[i][r].y = src[at];
+                                else carry[i][r].x = src[at];
                             }
                         }
                     }

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(NT) k_pass1(FilterArgs a) {
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, bool RAW, int N1, int N2, int B, int NT, int R2, bool XS>
+template <typename T, bool RAW, int N1, int N2, int B, int NT, int R2, int XS>
 __global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
     using P = Pass2<T, RAW, N1, N2, B, NT, R2, XS>;
     __shared__ __align__(16) char smem[P::SMEM];
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(NT) k_pass2(FilterArgs a) {
 // launch.  The two roles touch disjoint intermediates and disjoint units, and
 // their work-groups are interleaved so that every CU mixes the store-bound
 // pass 1 with the arithmetic-bound pass 2.
-template <typename T, int PH, int N1, int N2, int C, int B, int NT, bool XS>
+template <typename T, int PH, int N1, int N2, int C, int B, int NT, int XS>
 __global__ void __launch_bounds__(NT) k_step(FilterArgs a1, FilterArgs a2) {
     using P1 = Pass1<T, PH, P1_PRODUCT, N1, N2, C, NT>;
     using P2 = Pass2<T, false, N1, N2, B, NT, 16, XS>;
@@ -133,21 +133,23 @@ size_t cx_bytes(mf_precision prec) { return prec == MF_FP64 ? 16 : 8; }
 static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024 : x); }
 
 // Every (precision, N1, N2, C, B, R2, XS) instantiated (R2: largest radix of
-// the pass-2 stages, 16 or 8; it sets the pass-2 threads B N2 / R2.  XS: the
+// the pass-2 stages, 16 or 8; it sets the pass-2 threads B N2 / R2.  XS: 1 the
 // pass-2 stages exchange real and imaginary parts separately, in half the
-// LDS).  The first entry for each N and precision is its default plan.
+// LDS; 2 the same with bank-conflict-free layouts).  The first entry for each
+// N and precision is its default plan.
 #define MF_SHAPES(X)                                                                                              \
     X(float, 32, 32, 16, 32, 16, 0) X(float, 32, 64, 16, 32, 16, 0) X(float, 64, 64, 16, 64, 16, 0)                 \
     X(float, 64, 128, 16, 32, 16, 0) X(float, 128, 128, 16, 32, 16, 0) X(float, 128, 256, 16, 16, 16, 0)            \
     X(float, 256, 256, 16, 16, 16, 0) X(float, 256, 512, 16, 8, 16, 0) X(float, 512, 512, 16, 8, 16, 0)             \
-    X(float, 512, 1024, 16, 4, 16, 0) X(float, 256, 4096, 32, 1, 16, 1) X(float, 256, 4096, 16, 1, 16, 1)           \
+    X(float, 512, 1024, 16, 4, 16, 0) X(float, 256, 4096, 32, 1, 16, 2) X(float, 256, 4096, 16, 1, 16, 1)           \
     X(float, 256, 4096, 16, 1, 16, 0)                                                                              \
     X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 16, 1, 16, 1) X(float, 1024, 4096, 16, 1, 16, 0)        \
     X(float, 1024, 4096, 8, 1, 16, 0) X(float, 1024, 4096, 8, 1, 16, 1)                                           \
     X(float, 1024, 1024, 8, 4, 16, 0) X(float, 1024, 1024, 16, 8, 16, 0) X(float, 1024, 1024, 16, 4, 16, 0)         \
     X(float, 512, 2048, 16, 2, 16, 0) X(float, 2048, 512, 8, 8, 16, 0) X(float, 2048, 2048, 8, 2, 16, 0)            \
     X(float, 512, 8192, 16, 1, 16, 0) X(float, 256, 4096, 16, 1, 8, 0)                                             \
-    X(float, 1024, 4096, 8, 1, 8, 0)                                                                              \
+    X(float, 1024, 4096, 8, 1, 8, 0) X(float, 256, 4096, 32, 1, 16, 1) X(float, 256, 4096, 16, 1, 16, 2)          \
+    X(float, 1024, 4096, 16, 1, 16, 2)                                                                            \
     X(double, 32, 32, 8, 32, 16, 0) X(double, 32, 64, 8, 32, 16, 0) X(double, 64, 64, 8, 64, 16, 0)                 \
     X(double, 64, 128, 8, 32, 16, 0) X(double, 128, 128, 8, 32, 16, 0) X(double, 128, 256, 8, 16, 16, 0)            \
     X(double, 256, 256, 8, 16, 16, 0) X(double, 256, 512, 8, 8, 16, 0) X(double, 512, 512, 8, 8, 16, 0)             \
@@ -155,7 +157,8 @@ static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 102
     X(double, 512, 2048, 8, 2, 16, 0)                                                                              \
     X(double, 1024, 2048, 4, 2, 16, 0)                                                                             \
     X(double, 2048, 2048, 2, 2, 16, 0) X(double, 1024, 1024, 8, 4, 16, 0) X(double, 1024, 1024, 4, 4, 16, 0)        \
-    X(double, 1024, 1024, 4, 2, 16, 0) X(double, 512, 2048, 8, 2, 8, 0) X(double, 256, 4096, 8, 1, 16, 0)
+    X(double, 1024, 1024, 4, 2, 16, 0) X(double, 512, 2048, 8, 2, 8, 0) X(double, 256, 4096, 8, 1, 16, 0)         \
+    X(double, 256, 4096, 16, 1, 16, 2)
 
 static bool want(mf_precision prec, bool f64) { return (prec == MF_FP64) == f64; }
 
@@ -168,7 +171,7 @@ static void fill(Plan& p, int n1, int n2, int c1, int b2, int r2, int xs) {
     p.nt2 = clamp_threads(b2 * n2 / r2);
     p.log2n = ilog2((long long)n1 * n2);
     p.fused = p.nt1 == p.nt2;
-    p.split = xs != 0;
+    p.xs = xs;
 }
 
 int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
@@ -192,7 +195,7 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
 bool plan_supported(const Plan& q, mf_precision prec) {
 #define MF_MATCH(T, N1, N2, C, B, R2, XS)                                                                  \
     if (want(prec, std::is_same<T, double>::value) && q.n1 == N1 && q.n2 == N2 && q.c1 == C && q.b2 == B && \
-        q.nt2 == clamp_threads(B * N2 / R2) && q.split == (XS != 0))                                         \
+        q.nt2 == clamp_threads(B * N2 / R2) && q.xs == XS)                                                   \
         return true;
     MF_SHAPES(MF_MATCH)
 #undef MF_MATCH
@@ -221,6 +224,10 @@ Plan default_plan(int log2n, mf_precision prec) {
     size_t u = ((size_t)8 << 30) / bytes_per_unit;
     p.units = (int)(u < 1 ? 1 : (u > 4096 ? 4096 : u));
     p.fused = false;
+    // Pass 1 skips the stage-0 transform of narrow bands (bitwise the same
+    // result).  Measured on MI355X (32768 uneven templates x 4 segments, FP32):
+    // pass 1 1.495 -> 1.486 ms per 1024-unit launch; it is bound by its writes.
+    p.prune1 = true;
     return p;
 }
 
@@ -260,7 +267,7 @@ static hipError_t run_pass1(const FilterArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, bool RAW, int N1, int N2, int B, int R2, bool XS>
+template <typename T, bool RAW, int N1, int N2, int B, int R2, int XS>
 static hipError_t run_pass2(const FilterArgs& a, hipStream_t s) {
     static_assert(N1 % B == 0 && B <= N1, "pass-2 rows per work-group must tile N1");
     constexpr int NT = clamp_threads(B * N2 / R2);
@@ -285,15 +292,14 @@ hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const Filter
 hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s) {
 #define MF_P2(T, N1, N2, C, B, R2, XS)                                                                       \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B && \
-        p.nt2 == clamp_threads(B * N2 / R2) && p.split == (XS != 0))                                         \
-        return raw ? run_pass2<T, true, N1, N2, B, R2, XS != 0>(a, s)                                        \
-                   : run_pass2<T, false, N1, N2, B, R2, XS != 0>(a, s);
+        p.nt2 == clamp_threads(B * N2 / R2) && p.xs == XS)                                                   \
+        return raw ? run_pass2<T, true, N1, N2, B, R2, XS>(a, s) : run_pass2<T, false, N1, N2, B, R2, XS>(a, s);
     MF_SHAPES(MF_P2)
 #undef MF_P2
     return hipErrorInvalidValue;
 }
 
-template <typename T, int PH, int N1, int N2, int C, int B, bool XS>
+template <typename T, int PH, int N1, int N2, int C, int B, int XS>
 static hipError_t run_step(const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
     constexpr int NT1 = clamp_threads(C * N1 / 16), NT2 = clamp_threads(B * N2 / 16);
     if constexpr (NT1 == NT2) {
@@ -309,10 +315,10 @@ static hipError_t run_step(const FilterArgs& a1, const FilterArgs& a2, hipStream
 hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s) {
 #define MF_ST(T, N1, N2, C, B, R2, XS)                                                                         \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B &&   \
-        R2 == 16 && p.split == (XS != 0)) {                                                                   \
+        R2 == 16 && p.xs == XS) {                                                                             \
         if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
-            return run_step<float, 1, N1, N2, C, B, XS != 0>(a1, a2, s);                                       \
-        return run_step<T, 0, N1, N2, C, B, XS != 0>(a1, a2, s);                                               \
+            return run_step<float, 1, N1, N2, C, B, XS>(a1, a2, s);                                            \
+        return run_step<T, 0, N1, N2, C, B, XS>(a1, a2, s);                                                    \
     }
     MF_SHAPES(MF_ST)
 #undef MF_ST

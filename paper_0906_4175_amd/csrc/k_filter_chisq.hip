@@ -117,6 +117,11 @@ struct Pass2Band {
     static constexpr size_t SMEM =
         (size_t)(B * PN2 + TW + B * NS + B * HALF + TAB) * sizeof(cx<T>) + (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
+    // 4096-point rows, three radix-16 stages, one row per work-group: the
+    // exchanges use the bank-conflict-free layouts of the plain pass 2 (on
+    // complex values, where a half-wave must touch 32 distinct 8-byte slots).
+    static constexpr bool CF = N2 == 4096 && MAXR == 16 && B == 1 && NT == 256;
+    static_assert(!CF || PN2 >= kCfSlots, "conflict-free layout slots");
 
     template <int STEP>
     __device__ static __forceinline__ int off(int x, int r) {
@@ -236,7 +241,15 @@ struct Pass2Band {
                             const int k = j % NSPAN;
                             const cx<T>* src = buf + b * PN2;
 #pragma unroll
-                            for (int r = 0; r < R; ++r) v[i][r] = src[off<PER_ROW>(j, r)];
+                            for (int r = 0; r < R; ++r) {
+                                if constexpr (CF && s == 1) {
+                                    v[i][r] = src[cf_rd0(j, r)];
+                                } else if constexpr (CF) {
+                                    v[i][r] = src[cf_rd1(j, r)];
+                                } else {
+                                    v[i][r] = src[off<PER_ROW>(j, r)];
+                                }
+                            }
                             if constexpr (s >= 2 || !USE_F1) base = cmul(tw[tw_offset(N2, s, MAXR) + k], base);
                         }
                         cx<T> pw[R];
@@ -276,7 +289,11 @@ struct Pass2Band {
                             cx<T>* dst = buf + b * PN2;
 #pragma unroll
                             for (int r = 0; r < R; ++r) {
-                                if constexpr (NSPAN == 1 && R == 16) {
+                                if constexpr (CF && s == 0) {
+                                    dst[cf_wr0(j) ^ r] = v[i][r];
+                                } else if constexpr (CF) {
+                                    dst[cf_wr1(j, r)] = v[i][r];
+                                } else if constexpr (NSPAN == 1 && R == 16) {
                                     dst[pad16(idxD) + r] = v[i][r];
                                 } else {
                                     dst[off<NSPAN>(idxD, r)] = v[i][r];

@@ -201,7 +201,7 @@ mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]
     if (st != MF_OK) return st;
     if (!valid_prec(prec) || !plan) return fail(MF_E_ARG, "bad precision or null plan");
     const mf::Plan p = mf::select_plan(l, prec);
-    const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, (p.fused ? 1 : 0) | (p.split ? 2 : 0)};
+    const int32_t v[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, p.units, mf::plan_flags(p)};
     for (int i = 0; i < 8; ++i) plan[i] = v[i];
     return ok();
 }
@@ -217,7 +217,7 @@ int32_t mf_plan_candidates(const mf_grid* grid, mf_precision prec, int32_t* plan
     const int n = mf::plan_candidates(l, prec, v.data(), cap);
     for (int i = 0; i < n && i < cap; ++i) {
         const mf::Plan& p = v[(size_t)i];
-        const int32_t row[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, 0, (p.fused ? 1 : 0) | (p.split ? 2 : 0)};
+        const int32_t row[8] = {p.n1, p.n2, p.c1, p.b2, p.nt1, p.nt2, 0, mf::plan_flags(p)};
         for (int k = 0; k < 8; ++k) plans[8 * i + k] = row[k];
     }
     ok();
@@ -245,9 +245,14 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     const int nt16 = clampt((long long)q.b2 * q.n2 / 16), nt8 = clampt((long long)q.b2 * q.n2 / 8);
     q.nt2 = plan[5] == nt8 ? nt8 : nt16;
     q.units = plan[6];
-    if (plan[7] & ~3) return fail(MF_E_ARG, "plan flags %d: only bits 0 (pipelined step) and 1 (split exchange)", plan[7]);
+    if ((plan[7] & ~15) || (plan[7] & 6) == 4)
+        return fail(MF_E_ARG,
+                    "plan flags %d: bits 0 (pipelined step), 1 (split exchange), 2 (conflict-free layouts, with bit 1), "
+                    "3 (narrow-band pass 1)",
+                    plan[7]);
     q.fused = (plan[7] & 1) != 0;
-    q.split = (plan[7] & 2) != 0;
+    q.xs = (plan[7] & 4) ? 2 : ((plan[7] & 2) ? 1 : 0);
+    q.prune1 = (plan[7] & 8) != 0;
     if ((int64_t)q.n1 * q.n2 != grid->n || !mf::plan_supported(q, prec))
         return fail(MF_E_UNSUPPORTED,
                     "plan %dx%d c=%d b=%d (pass-2 threads %d, flags %d) is not built for this N/precision", q.n1, q.n2,
@@ -355,11 +360,13 @@ mf_status mf_spa_bank(const mf_grid* grid, const double* mc_host, const double* 
 namespace {
 
 // Body of mf_filter; ev_keys (nullable, zeroed by the caller) turns on the
-// per-window event keys of pass 2.
+// per-window event keys of pass 2; plan_in (nullable) replaces the selected
+// launch plan.
 mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
                       int64_t n_seg, const double* Sn_dev, mf_precision prec, const mf_filter_opts* opts,
                       void* workspace_dev, size_t workspace_bytes, mf_peak* peaks_dev, void* rho_dev,
-                      mf_stream_t stream, unsigned long long* ev_keys, int ev_log2w) {
+                      mf_stream_t stream, unsigned long long* ev_keys, int ev_log2w,
+                      const mf::Plan* plan_in = nullptr) {
     int l, klo;
     mf_status st = check_grid(grid, &l, &klo);
     if (st != MF_OK) return st;
@@ -380,7 +387,7 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
     if (o.n_series > 0 && (!o.series_units_dev || !rho_dev))
         return fail(MF_E_ARG, "series requested without series_units_dev / rho_dev");
     if (((uintptr_t)workspace_dev & 255) != 0) return fail(MF_E_ARG, "workspace must be 256-byte aligned");
-    const mf::Plan p = mf::select_plan(l, prec);
+    const mf::Plan p = plan_in ? *plan_in : mf::select_plan(l, prec);
     if (p.log2n != l || (int64_t)p.n1 * p.n2 != n || p.n2 % p.c1 != 0 || p.n1 % p.b2 != 0 ||
         !mf::plan_supported(p, prec))
         return fail(MF_E_UNSUPPORTED, "no plan for n=%lld", (long long)n);
@@ -410,6 +417,7 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
     a.ev_keys = ev_keys;
     a.ev_log2w = ev_log2w;
     a.tw2 = ws + L.off_tw2;
+    a.prune1 = p.prune1 ? 1 : 0;
 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);

@@ -26,8 +26,14 @@ struct Plan {
     int nt2;         // threads per pass-2 work-group
     int units;       // (template, segment) units per batch
     bool fused;      // pipelined step kernel (pass 1 of batch b with pass 2 of batch b-1)
-    bool split;      // pass-2 stages exchange real and imaginary parts separately
+    int xs;          // pass-2 exchange: 0 complex values, 1 real and imaginary parts one
+                     // after the other (half the LDS), 2 as 1 with bank-conflict-free layouts
+    bool prune1;     // pass 1 skips the stage-0 transform where a band has only rows k1 < N1/16
 };
+// plan flags (last entry of the public plan array)
+inline int plan_flags(const Plan& p) {
+    return (p.fused ? 1 : 0) | (p.xs >= 1 ? 2 : 0) | (p.xs == 2 ? 4 : 0) | (p.prune1 ? 8 : 0);
+}
 
 Plan default_plan(int log2n, mf_precision prec);
 bool plan_supported(const Plan& p, mf_precision prec);
@@ -80,6 +86,7 @@ struct FilterArgs {
     unsigned long long* ev_keys;  // [n_units][n >> ev_log2w], unit u = s * n_tmpl + t
     int32_t ev_log2w;
     const void* tw2;              // [kTw2Radix - 1][kTw2Span] last-stage factors (see pass2_uses_tw2)
+    int32_t prune1;               // pass 1 skips the stage-0 transform of narrow bands (plan flag bit 3)
 };
 
 // Workspace carve-up of mf_filter_chisq (band mode).

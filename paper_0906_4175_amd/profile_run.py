@@ -24,7 +24,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--precision", default="fp32_ph64")
+    ap.add_argument("--precision", default="fp32_ph64",
+                    help="precision, or several separated by commas (run one after the other)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--chisq-bands", type=int, default=0, help="also run the chi^2 band mode with p bands")
     args = ap.parse_args()
@@ -55,29 +56,31 @@ def main():
     rngs = synth.rngs(args.workload, wl.n_seg)
     segs = [synth.coloured_noise(Sh[k_lo: wl.n // 2], grid.df, k_lo, wl.n // 2 + 1, rngs[i], dtype=np.complex64)
             for i in range(wl.n_seg)]
-    st = torch.from_numpy(np.stack(segs)).to(dev)
-    if args.precision == "fp64":
-        st = st.to(torch.complex128)
+    st32 = torch.from_numpy(np.stack(segs)).to(dev)
     if args.workload == 2:
         mc, eta = synth.bank_mc_eta_grid()
     else:
         mc, eta, _, _ = synth.bank_uneven({3: 8192, 5: 32768}[args.workload], synth.rngs(args.workload, 1)[0])
-    bank = mf.spa_bank(grid, mc, eta, Sn, args.precision)
-    ws = torch.empty(mf.filter_workspace_bytes(grid, args.precision, bank.n_tmpl, wl.n_seg), dtype=torch.uint8,
-                     device=dev)
-    for _ in range(args.steps):
-        res = mf.filter(grid, bank, st, Sn, args.precision, workspace=ws)
-    torch.cuda.synchronize()
-    if args.chisq_bands > 0:
-        del ws
-        _, P = mf.psd(grid, prefix=True, device=dev)
-        wsb = torch.empty(mf.filter_chisq_workspace_bytes(grid, args.precision, bank.n_tmpl, wl.n_seg,
-                                                          args.chisq_bands), dtype=torch.uint8, device=dev)
+    for prec in args.precision.split(","):
+        st = st32.to(torch.complex128) if prec == "fp64" else st32
+        bank = mf.spa_bank(grid, mc, eta, Sn, prec)
+        ws = torch.empty(mf.filter_workspace_bytes(grid, prec, bank.n_tmpl, wl.n_seg), dtype=torch.uint8,
+                         device=dev)
         for _ in range(args.steps):
-            mf.filter_chisq(grid, bank, st, Sn, P, args.precision, p_bands=args.chisq_bands, workspace=wsb)
+            res = mf.filter(grid, bank, st, Sn, prec, workspace=ws)
         torch.cuda.synchronize()
-    print(f"profile_run done: copy {args.copy_mib} MiB, {args.steps} steps of {wl.name}, "
-          f"max rho {float(res['rho'].max()):.4f}")
+        del ws
+        if args.chisq_bands > 0:
+            _, P = mf.psd(grid, prefix=True, device=dev)
+            wsb = torch.empty(mf.filter_chisq_workspace_bytes(grid, prec, bank.n_tmpl, wl.n_seg,
+                                                              args.chisq_bands), dtype=torch.uint8, device=dev)
+            for _ in range(args.steps):
+                mf.filter_chisq(grid, bank, st, Sn, P, prec, p_bands=args.chisq_bands, workspace=wsb)
+            torch.cuda.synchronize()
+            del wsb
+        print(f"profile_run: {args.steps} steps of {wl.name} in {prec}, max rho {float(res['rho'].max()):.4f}",
+              flush=True)
+    print(f"profile_run done: copy {args.copy_mib} MiB, {wl.name}")
 
 
 def run_gradient(args, mf, synth, dev):
