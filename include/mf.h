@@ -242,6 +242,31 @@ mf_status mf_filter(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
                     mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream);
 
 /*
+ * mf_filter_noalloc -- mf_filter for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as mf_filter, minus
+ * the workspace: the call uses a static device array of
+ * MF_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends, and calls no allocator.  The units per batch are
+ * the plan's, lowered until one batch of intermediates fits the array (at
+ * N = 2^20 in the FP32 modes, 63 units per batch for one segment), so the
+ * results are bitwise those of mf_filter.
+ *   stream  must belong to the current device (else MF_E_ARG).
+ * Every call on a GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams, host threads) race and their results are
+ * undefined; calls ordered on one stream are safe.  The array keeps the last
+ * call's contents; every value a call reads is written by that call first.
+ * Errors: those of mf_filter; MF_E_WORKSPACE if one unit per batch plus the
+ * per-segment weights and per-unit peak records exceed the array;
+ * MF_E_HIP if the array's address cannot be looked up.
+ */
+#define MF_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+mf_status mf_filter_noalloc(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
+                            const void* stilde_dev, int64_t n_seg, const double* Sn_dev,
+                            mf_precision prec, const mf_filter_opts* opts,
+                            mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream);
+
+/*
  * mf_ifft -- the unnormalised complex inverse DFT z_j = sum_k q_k e^{+2 pi i jk/N}
  * of `batch` contiguous N-point arrays, with the same two-pass kernels the
  * filter uses (diagnostic / test entry point).  q_dev and z_dev are

@@ -196,6 +196,16 @@ def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, preci
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     if peaks is None:
         peaks = torch.empty(2 * n_units, dtype=torch.float64, device=dev)
+    opts, series, su = _filter_opts(grid, prec, dev, threshold, window, series_units)
+    g = grid.c()
+    st = _clib.mf_filter(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn), prec,
+                        C.byref(opts), _ptr(workspace), workspace.numel(), _ptr(peaks), _ptr(series), _stream(dev))
+    L.check(st)
+    return _peaks_dict(peaks, bank.n_tmpl, n_seg, series)
+
+
+def _filter_opts(grid: Grid, prec: int, dev, threshold, window, series_units):
+    """mf_filter_opts and the series buffer (the unit-id tensor is returned to keep it alive)."""
     opts = L.MfFilterOpts(float(threshold), 0, 0, None, 0)
     if window is not None:
         opts.j_begin, opts.j_end = int(window[0]), int(window[1])
@@ -207,13 +217,39 @@ def filter(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, preci
                              device=dev)
         opts.series_units_dev = su.data_ptr()
         opts.n_series = su.numel()
-    g = grid.c()
-    st = _clib.mf_filter(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn), prec,
-                        C.byref(opts), _ptr(workspace), workspace.numel(), _ptr(peaks), _ptr(series), _stream(dev))
-    L.check(st)
-    pk = peaks.view(bank.n_tmpl, n_seg, 2)
-    ints = pk[..., 1].contiguous().view(torch.int32).view(bank.n_tmpl, n_seg, 2)
+    return opts, series, su
+
+
+def _peaks_dict(peaks: torch.Tensor, n_tmpl: int, n_seg: int, series):
+    pk = peaks.view(n_tmpl, n_seg, 2)
+    ints = pk[..., 1].contiguous().view(torch.int32).view(n_tmpl, n_seg, 2)
     return {"rho": pk[..., 0], "j": ints[..., 0], "n_above": ints[..., 1], "series": series, "raw": peaks}
+
+
+def filter_noalloc(grid: Grid, bank: Bank, stilde: torch.Tensor, Sn: torch.Tensor, peaks: torch.Tensor,
+                   precision="fp32_ph64", threshold: float = math.inf, window=None, series_ptr: int = 0,
+                   series_units_ptr: int = 0, n_series: int = 0):
+    """:func:`filter` through mf_filter_noalloc: the library's static device
+    scratch instead of a workspace.  The caller passes every buffer (peaks
+    [2 n_tmpl n_seg] float64; optional series and unit ids as device
+    pointers), so the call allocates nothing."""
+    prec = _prec(precision)
+    _require_cuda(stilde, Sn, peaks)
+    if stilde.dim() == 1:
+        stilde = stilde.unsqueeze(0)
+    if stilde.dtype != _cdtype(prec) or not stilde.is_contiguous() or stilde.shape[-1] != grid.n // 2 + 1:
+        raise ValueError(f"stilde must be contiguous {_cdtype(prec)} of shape [n_seg, {grid.n // 2 + 1}]")
+    n_seg = int(stilde.shape[0])
+    if peaks.dtype != torch.float64 or not peaks.is_contiguous() or peaks.numel() < 2 * bank.n_tmpl * n_seg:
+        raise ValueError("peaks must be contiguous float64 with 2 n_tmpl n_seg elements")
+    opts = L.MfFilterOpts(float(threshold), 0, 0, series_units_ptr or None, int(n_series))
+    if window is not None:
+        opts.j_begin, opts.j_end = int(window[0]), int(window[1])
+    g = grid.c()
+    st = _clib.mf_filter_noalloc(C.byref(g), _ptr(bank.data), bank.n_tmpl, _ptr(stilde), n_seg, _ptr(Sn), prec,
+                                 C.byref(opts), _ptr(peaks), C.c_void_p(series_ptr or None), _stream(stilde.device))
+    L.check(st)
+    return _peaks_dict(peaks, bank.n_tmpl, n_seg, None)
 
 
 def filter_chisq_workspace_bytes(grid: Grid, precision, n_tmpl: int, n_seg: int, p_bands: int = 16) -> int:

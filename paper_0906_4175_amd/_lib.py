@@ -37,6 +37,10 @@ class MfBankEntry(C.Structure):
                 ("inv_sigma", C.c_float), ("reserved", C.c_int32)]
 
 
+# size of the static device array mf_filter_noalloc works in (mf.h)
+MF_NOALLOC_SCRATCH_BYTES = 512 << 20
+
+
 class MfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -50,7 +54,7 @@ EXPORTS = [
     "mf_template_metric", "mf_chisq", "mf_filter_chisq", "mf_filter_chisq_workspace_bytes",
     "mf_psd_prefix", "mf_rfft", "mf_rfft_workspace_bytes",
     "mf_filter_events", "mf_filter_events_workspace_bytes", "mf_chisq_events", "mf_timing_read_split",
-    "mf_filter_chisq_plan", "mf_set_band_plan",
+    "mf_filter_chisq_plan", "mf_set_band_plan", "mf_filter_noalloc",
 ]
 
 _lib = None
@@ -81,6 +85,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mf_spa_bank.argtypes = [P(MfGrid), P(dbl), P(dbl), i64, vp, C.c_int, C.c_int, vp, P(i32), P(dbl), vp, vp]
     lib.mf_filter.restype = C.c_int
     lib.mf_filter.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, C.c_int, P(MfFilterOpts), vp, sz, vp, vp, vp]
+    lib.mf_filter_noalloc.restype = C.c_int
+    lib.mf_filter_noalloc.argtypes = [P(MfGrid), vp, i64, vp, i64, vp, C.c_int, P(MfFilterOpts), vp, vp, vp]
     lib.mf_ifft_workspace_bytes.restype = sz
     lib.mf_ifft_workspace_bytes.argtypes = [i64, C.c_int, i64]
     lib.mf_ifft.restype = C.c_int

@@ -472,6 +472,60 @@ size_t events_scratch_bytes(int64_t n, int64_t n_tmpl, int64_t n_seg, int log2w)
     return al(keys) + al(unit_ev) + al(best);
 }
 
+// Scratch of mf_filter_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, resident until the process ends.  Host code never
+// passes its name to a kernel: it uses the address hipGetSymbolAddress
+// returns for the current device (kept per device below).
+static __device__ __align__(256) unsigned char scratch[MF_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device ordinal -> address of that device's copy
+
+// Address of the current device's scratch; the first call on a device looks
+// it up (with that device current) and keeps it.
+mf_status scratch_address(mf_stream_t stream, void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "mf_filter_noalloc device");
+    if (stream) {
+        int sdev = -1;
+        e = hipStreamGetDevice((hipStream_t)stream, &sdev);
+        if (e != hipSuccess) return hip_fail(e, "mf_filter_noalloc stream device");
+        if (sdev != dev) return fail(MF_E_ARG, "stream belongs to device %d, current device is %d", sdev, dev);
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "mf_filter_noalloc scratch address");
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(MF_E_HIP, "mf_filter_noalloc: unaligned scratch");
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return MF_OK;
+}
+
+mf::Plan with_units(mf::Plan p, int64_t units) {
+    p.units = (int)units;
+    return p;
+}
+
+// The largest units-per-batch, at most the plan's, whose workspace fits the
+// static scratch; false if not even one unit per batch fits.
+bool scratch_units(const mf::Plan& p, mf_precision prec, int64_t n, int64_t n_tmpl, int64_t n_seg, int64_t* units) {
+    const size_t cap = (size_t)MF_NOALLOC_SCRATCH_BYTES;
+    if (mf::filter_layout(with_units(p, 1), prec, n, n_tmpl, n_seg).total > cap) return false;
+    int64_t lo = 1, hi = p.units;  // invariant: lo fits
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (mf::filter_layout(with_units(p, mid), prec, n, n_tmpl, n_seg).total <= cap) lo = mid;
+        else hi = mid - 1;
+    }
+    *units = lo;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -532,6 +586,32 @@ mf_status mf_filter_events(const mf_grid* grid, const void* bank_dev, int64_t n_
                           unit_ev, best, seg_events_dev, s);
     if (e != hipSuccess) return hip_fail(e, "mf_filter_events clustering");
     return ok();
+}
+
+mf_status mf_filter_noalloc(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl, const void* stilde_dev,
+                            int64_t n_seg, const double* Sn_dev, mf_precision prec, const mf_filter_opts* opts,
+                            mf_peak* peaks_dev, void* rho_dev, mf_stream_t stream) {
+    int l, klo;
+    mf_status st = check_grid(grid, &l, &klo);
+    if (st != MF_OK) return st;
+    if (!bank_dev || !stilde_dev || !Sn_dev || !peaks_dev) return fail(MF_E_ARG, "null pointer argument");
+    if (!valid_prec(prec)) return fail(MF_E_ARG, "bad precision %d", (int)prec);
+    if (n_tmpl < 1 || n_seg < 1 || n_tmpl * n_seg > (int64_t(1) << 40))
+        return fail(MF_E_ARG, "n_tmpl=%lld n_seg=%lld", (long long)n_tmpl, (long long)n_seg);
+    mf::Plan p = mf::select_plan(l, prec);
+    int64_t units;
+    if (!scratch_units(p, prec, grid->n, n_tmpl, n_seg, &units))
+        return fail(MF_E_WORKSPACE,
+                    "request needs %zu bytes of scratch at one unit per batch; the static scratch holds %zu "
+                    "(MF_NOALLOC_SCRATCH_BYTES)",
+                    mf::filter_layout(with_units(p, 1), prec, grid->n, n_tmpl, n_seg).total,
+                    (size_t)MF_NOALLOC_SCRATCH_BYTES);
+    p = with_units(p, units);
+    void* ws = nullptr;
+    st = scratch_address(stream, &ws);
+    if (st != MF_OK) return st;
+    return filter_impl(grid, bank_dev, n_tmpl, stilde_dev, n_seg, Sn_dev, prec, opts, ws,
+                       (size_t)MF_NOALLOC_SCRATCH_BYTES, peaks_dev, rho_dev, stream, nullptr, 0, &p);
 }
 
 size_t mf_ifft_workspace_bytes(int64_t n, mf_precision prec, int64_t batch) {

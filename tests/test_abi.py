@@ -118,6 +118,23 @@ def test_filter_workspace_and_window_validation(lib):
     assert lib.mf_filter(*args(need)[:6], 9, *args(need)[7:]) == -1  # bad precision
 
 
+def test_noalloc_validation_before_any_device_call(lib):
+    # rejected on the host before the scratch is looked up (no GPU needed)
+    g = _grid()
+    ptr = C.c_void_p(256)
+    assert lib.mf_filter_noalloc(C.byref(g), None, 4, ptr, 1, ptr, 1, None, ptr, None, None) == -1
+    assert lib.mf_filter_noalloc(C.byref(g), ptr, 4, ptr, 1, ptr, 9, None, ptr, None, None) == -1
+    assert lib.mf_filter_noalloc(C.byref(g), ptr, 0, ptr, 1, ptr, 1, None, ptr, None, None) == -1
+    # FP64 at N = 2^22: the weights of 17 segments alone exceed the static scratch
+    g22 = _grid(n=1 << 22)
+    need_w = 17 * ((1 << 21) + 1) * 16
+    assert need_w > L.MF_NOALLOC_SCRATCH_BYTES
+    assert lib.mf_filter_noalloc(C.byref(g22), ptr, 1, ptr, 17, ptr, 0, None, ptr, None, None) == -5
+    assert b"static scratch" in lib.mf_last_error()
+    # the FP64 peak partials of a very large bank do not fit either
+    assert lib.mf_filter_noalloc(C.byref(g), ptr, 200000, ptr, 1, ptr, 0, None, ptr, None, None) == -5
+
+
 def test_ifft_and_grad_validation(lib):
     assert lib.mf_ifft_workspace_bytes(1000, 1, 1) == 0
     assert lib.mf_ifft(1 << 12, 1, None, C.c_void_p(256), 1, C.c_void_p(256), 1 << 20, None) == -1
