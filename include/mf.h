@@ -140,8 +140,13 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
  * other through half the LDS (more work-groups per CU); bit 2 (with bit 1):
  * that exchange uses bank-conflict-free layouts (4096-point rows); bit 3:
  * pass 1 skips its first column stage for templates whose band lies below
- * row N1/16 (every such butterfly has one non-zero input).  Every plan gives
- * bitwise the same results.
+ * row N1/16 (every such butterfly has one non-zero input); bit 4: pass 1
+ * multiplies its output by the part of the four-step factor that the first
+ * row stage of pass 2 would apply (a function of the row and of the block of
+ * N2/R0 columns, R0 the first row radix), so that stage has no factor (needs
+ * the pass-1 columns to divide N2/R0).  Bits 0-3 give bitwise the same
+ * results; bit 4 moves one complex product from pass 2 to pass 1 (results
+ * agree to rounding).
  */
 mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 

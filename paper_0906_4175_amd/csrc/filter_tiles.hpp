@@ -85,6 +85,25 @@ __device__ __forceinline__ bool better64(double zz, int j, double bzz, int bj) {
     return zz > bzz || (zz == bzz && j < bj);
 }
 
+// Template and segment of unit u = s n_tmpl + t with one division.  The
+// operands are wave-uniform, so the 64-bit division runs on the scalar unit
+// (a 32-bit one would go through the vector unit's float reciprocal).
+__device__ __forceinline__ void unit_split(int64_t u, int64_t n_tmpl, int64_t& t, int64_t& s) {
+    s = u / n_tmpl;
+    t = u - s * n_tmpl;
+}
+
+// digit_weight(L, st) for a run-time stage index st < num_stages(L) (a chain
+// of selects between compile-time constants instead of a loop).
+template <int L, int MAXR>
+__device__ __forceinline__ int digit_weight_rt(int st) {
+    int w = 0;
+    static_for<0, num_stages(L, MAXR)>([&](auto S_) {
+        if (st == decltype(S_)::value) w = digit_weight(L, decltype(S_)::value, MAXR);
+    });
+    return w;
+}
+
 // ---------------------------------------------------------------------------
 // Pass 1 tile: C adjacent columns k2 of one unit.
 // PH: 0 = FP64 phase, 1 = FP32 phase.  MODE: P1_PRODUCT transforms the
@@ -124,13 +143,17 @@ struct Pass1 {
     static constexpr bool NARROW_OK = MODE == P1_PRODUCT && XS && NS == 2 && radix_at(N1, 0) == 16 &&
                                       radix_at(N1, 1) == 16 && C * N1 / 16 == NT;
     static constexpr size_t BUF_BYTES = (size_t)N1 * C * (XS ? sizeof(T) : sizeof(cx<T>));
-    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1) * sizeof(cx<T>);
+    // PRE (product mode, FilterArgs::pre0_r0 > 0): the factor pass 2's first
+    // stage would apply to this tile's columns, one per output row j1
+    static constexpr int PRE = MODE == P1_PRODUCT ? N1 : 0;
+    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1 + PRE) * sizeof(cx<T>);
 
     __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
         cx<T>* buf = (cx<T>*)smem;
         T* fbuf = (T*)smem;
         cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);
         cx<T>* t1 = tw + TW;  // [k][r]
+        cx<T>* tpre = t1 + T1;  // PRE: [j1]
         [[maybe_unused]] cx<T> carry[XS ? EPT : 1];
         const int tid = threadIdx.x;
         const int k2_0 = tile * C;
@@ -146,8 +169,8 @@ struct Pass1 {
         if constexpr (RAW) {
             qin = (const cx<T>*)a.raw_in + u * N;
         } else {
-            const int64_t t = u % a.n_tmpl;
-            const int64_t s = u / a.n_tmpl;
+            int64_t t, s;
+            unit_split(u, a.n_tmpl, t, s);
             const mf_bank_entry e = a.bank[t];
             coef = load_coef(e);
             klo = e.k_lo;
@@ -167,6 +190,20 @@ struct Pass1 {
         }
         cx<T>* inter = (cx<T>*)a.inter + ul * N;
         [[maybe_unused]] const bool narrow = NARROW_OK && a.prune1 != 0 && khi < (N1 / 16) * N2;
+        // PRE: row j1 of this tile's columns k2 (all in one block of N2/R0, so
+        // rr = floor(k2 / (N2/R0)) is the tile's) takes e^{2 pi i j1 rr / (N1 R0)}
+        [[maybe_unused]] const bool pre = PRE > 0 && a.pre0_r0 > 0;
+        auto fill_pre = [&]() {
+            if constexpr (PRE > 0) {
+                if (pre) {
+                    const int r0 = a.pre0_r0;
+                    const int rr = k2_0 / (N2 / r0);
+                    const int mask = N1 * r0 - 1;  // N1 R0 is a power of two
+                    const T inv = (T)1 / (T)(N1 * r0);
+                    for (int q = tid; q < N1; q += NT) tpre[q] = root_of_unity((T)((q * rr) & mask) * inv);
+                }
+            }
+        };
 
         static_for<0, NS>([&](auto S_) {
             constexpr int s = decltype(S_)::value;
@@ -196,6 +233,7 @@ struct Pass1 {
                         const int kk = q / R1, r = q % R1;
                         t1[q] = root_of_unity((T)((kk * r) & (16 * R1 - 1)) * INV_M1);
                     }
+                    fill_pre();
                     // stage-1 input r of every butterfly of column c is the product of row r
 #pragma unroll
                     for (int part = 0; part < 2; ++part) {
@@ -288,6 +326,7 @@ struct Pass1 {
                     const int k = q / R1, r = q % R1;
                     t1[q] = root_of_unity((T)((k * r) & (16 * R1 - 1)) * INV_M1);
                 }
+                fill_pre();
             }
             if constexpr (s == NS - 1) {
 #pragma unroll
@@ -298,7 +337,13 @@ struct Pass1 {
                         const int j = bf / C;
                         cx<T>* dst = inter + (int64_t)j * N2 + k2_0 + c;
 #pragma unroll
-                        for (int r = 0; r < R; ++r) dst[(int64_t)r * NSPAN * N2] = v[i][r];
+                        for (int r = 0; r < R; ++r) {
+                            cx<T> y = v[i][r];
+                            if constexpr (PRE > 0) {
+                                if (pre) y = cmul(y, tpre[j + r * NSPAN]);  // output r is row j1 = j + r NSPAN
+                            }
+                            dst[(int64_t)r * NSPAN * N2] = y;
+                        }
                     }
                 }
             } else if constexpr (XS) {
@@ -421,8 +466,18 @@ struct Pass2 {
     static constexpr bool TAB2 =
         F64 && !RAW && N2 == kTw2Span * kTw2Radix && MAXR == 16 && B == 1 && NT == 256 && NS == 3;
     static constexpr int TWL = TAB2 ? 15 * 16 : TW;
+    // F1 (FP32 and the other non-TAB2 shapes of at least two stages, one
+    // table entry per thread): stage 1 reads its factors (w_1 t^{weight_1})^r
+    // from a per-row table [B][R1 - 1][span_1] of exactly reduced roots,
+    // filled once per work-group during stage 0, instead of a product tree of
+    // powers per butterfly (15 table reads for 14 complex products and one
+    // twiddle product).
+    static constexpr int R1 = NS >= 2 ? radix_at(N2, 1, MAXR) : 1;
+    static constexpr int SPAN1 = NS >= 2 ? span_before(N2, 1, MAXR) : 0;
+    static constexpr bool F1 = !TAB2 && NS >= 2 && B * (R1 - 1) * SPAN1 <= NT;
+    static constexpr int NF1 = F1 ? B * (R1 - 1) * SPAN1 : 0;
     static constexpr size_t BUF_BYTES = (size_t)B * PN2 * (SPLIT ? sizeof(T) : sizeof(cx<T>));
-    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TWL + B * NS + B * R0) * sizeof(cx<T>) +
+    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TWL + B * NS + B * R0 + NF1) * sizeof(cx<T>) +
                                    (size_t)NWAVE * (8 + 8 + 4 + 4);
     static_assert(B * NS <= NT, "one thread per (row, stage) factor");
 
@@ -442,7 +497,8 @@ struct Pass2 {
         cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);  // TAB2: [r - 1][k] stage-1 factors
         cx<T>* trow = tw + TWL;  // [B][NS]: t^{weight_s} per row
         cx<T>* pow0 = trow + B * NS;  // [B][R0]: (t^{weight_0})^r, the stage-0 factors of each row
-        unsigned long long* red_key = (unsigned long long*)(pow0 + B * R0);
+        cx<T>* f1 = pow0 + B * R0;    // F1: [B][R1 - 1][span_1] stage-1 factors
+        unsigned long long* red_key = (unsigned long long*)(f1 + NF1);
         double* red_zz = (double*)(red_key + NWAVE);
         int* red_j = (int*)(red_zz + NWAVE);
         unsigned int* red_cnt = (unsigned int*)(red_j + NWAVE);
@@ -453,13 +509,13 @@ struct Pass2 {
 
         if (!TAB2 && tid < B * NS) {
             const int b = tid / NS, st = tid % NS;
-            const int64_t m = (int64_t)(rb * B + b) * digit_weight(N2, st, MAXR);  // < N
+            const int m = (rb * B + b) * digit_weight_rt<N2, MAXR>(st);  // < N <= 2^22
             trow[b * NS + st] = root_of_unity((T)m / (T)N);
         }
         for (int q = tid; q < B * R0; q += NT) {
             // each power from its exactly reduced argument (no product chain)
             const int b = q / R0, r = q % R0;
-            const int64_t m = ((int64_t)(rb * B + b) * digit_weight(N2, 0, MAXR) * r) & (N - 1);
+            const int m = ((rb * B + b) * digit_weight(N2, 0, MAXR) * r) & (int)(N - 1);  // < N1 N2 <= 2^22
             pow0[q] = root_of_unity((T)m / (T)N);
         }
 
@@ -470,14 +526,15 @@ struct Pass2 {
         float inv_sigma_f = 1.0f;
         int slot = -1;
         if constexpr (!RAW) {
-            const int64_t t = u % a.n_tmpl;
+            int64_t t, sg;
+            unit_split(u, a.n_tmpl, t, sg);
             const mf_bank_entry e = a.bank[t];
             sigma = e.sigma;
             inv_sigma_f = e.inv_sigma;
             const double th = a.rho_threshold * sigma;
             thr2 = (T)(th * th);
             count_on = a.rho_threshold < INFINITY;
-            const int64_t pub = t * a.n_seg + u / a.n_tmpl;  // public unit id t * n_seg + s
+            const int64_t pub = t * a.n_seg + sg;  // public unit id t * n_seg + s
             for (int i = 0; i < a.n_series; ++i)
                 if (a.series_units[i] == pub) slot = i;
         }
@@ -511,18 +568,29 @@ struct Pass2 {
                     const int j = bf % PER_ROW;
                     const int b = bf / PER_ROW;
                     if constexpr (s == 0) {
-                        const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
+                        // 32-bit byte offsets from the unit's base (a unit is at most
+                        // 2^22 complex values), so the loads address from a scalar base
+                        const char* ibase = (const char*)inter;
+                        const unsigned int o0 = (unsigned int)(((rb * B + b) * N2 + j) * (int)sizeof(cx<T>));
 #pragma unroll
-                        for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
+                        for (int r = 0; r < R; ++r)
+                            v[i][r] = *(const cx<T>*)(ibase + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>))));
                         if constexpr (TAB2) {
                             // input r is k2 = j + PER_ROW r: t^{k2} = t^j (t^{PER_ROW})^r
+                            // (pass 1 already applied (t^{PER_ROW})^r when a.pre0_r0 is set)
                             const int64_t m = ((int64_t)(rb * B + b) * j) & (N - 1);
                             const cx<T> tj = root_of_unity((T)m / (T)N);
-                            v[i][0] = cmul(v[i][0], tj);
+                            if (a.pre0_r0 > 0) {
 #pragma unroll
-                            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], cmul(pow0[b * R0 + r], tj));
-                        } else {
+                                for (int r = 0; r < R; ++r) v[i][r] = cmul(v[i][r], tj);
+                            } else {
+                                v[i][0] = cmul(v[i][0], tj);
+#pragma unroll
+                                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], cmul(pow0[b * R0 + r], tj));
+                            }
+                        } else if (a.pre0_r0 == 0) {
                             // stage 0 has no stage twiddle: its factors are the row's table
+                            // (pass 1 applied them when a.pre0_r0 is set)
 #pragma unroll
                             for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], pow0[b * R0 + r]);
                         }
@@ -544,6 +612,10 @@ struct Pass2 {
                             const cx<T>* t2 = (const cx<T>*)a.tw2;
 #pragma unroll
                             for (int r = 1; r < R; ++r) p[r] = t2[(r - 1) * NSPAN + k];
+                        } else if constexpr (F1 && s == 1) {
+                            const cx<T>* f = f1 + b * (R1 - 1) * SPAN1 + k;
+#pragma unroll
+                            for (int r = 1; r < R; ++r) p[r] = f[(r - 1) * SPAN1];
                         } else {
                             powers<R>(cmul(tw[tw_offset(N2, s, MAXR) + k], trow[b * NS + s]), p);
                         }
@@ -562,6 +634,18 @@ struct Pass2 {
                     }
                 } else {
                     fill_stage_twiddles<T, N2, MAXR>(tw, tid, NT);
+                }
+                if constexpr (F1) {
+                    // entry (b, r, k): exponent r dw_1 (k N1 + j1) mod N, the stage-1 factor
+                    // (w_1^k t^{dw_1})^r of input r at span position k of row j1 = rb B + b
+                    if (tid < NF1) {
+                        const int b = tid / ((R1 - 1) * SPAN1), rk = tid % ((R1 - 1) * SPAN1);
+                        const int r = rk / SPAN1 + 1, k = rk % SPAN1;
+                        constexpr int DW1 = digit_weight(N2, 1, MAXR);
+                        const int m = (int)(((unsigned int)r * (unsigned int)(DW1 * (k * N1 + rb * B + b))) &
+                                            (unsigned int)(N - 1));
+                        f1[tid] = root_of_unity((T)m / (T)N);
+                    }
                 }
             }
             if constexpr (s == NS - 1) {
@@ -685,9 +769,13 @@ struct Pass2 {
                             const int idxD = (j / NSPAN) * NSPAN * R + (j % NSPAN);
                             T* dst = fbuf + b * PN2;
                             if constexpr (CF && s == 0) {
-                                const int w0 = cf_wr0(j);
+                                // byte offsets: (w0 ^ r) * 4 = (w0 * 4) ^ (r * 4), one xor per store
+                                unsigned int a0 = (unsigned int)cf_wr0(j) * (unsigned int)sizeof(T);
+                                asm volatile("" : "+v"(a0));  // keep the xor on the scaled offset
+                                char* d = (char*)dst;
 #pragma unroll
-                                for (int r = 0; r < R; ++r) dst[w0 ^ r] = part ? v[i][r].y : v[i][r].x;
+                                for (int r = 0; r < R; ++r)
+                                    *(T*)(d + (a0 ^ (unsigned int)(r * sizeof(T)))) = part ? v[i][r].y : v[i][r].x;
                             } else if constexpr (CF) {
 #pragma unroll
                                 for (int r = 0; r < R; ++r) dst[cf_wr1(j, r)] = part ? v[i][r].y : v[i][r].x;
@@ -749,12 +837,9 @@ struct Pass2 {
             if (full_window) {
                 const int lane = tid & 63;
                 const int wave = tid >> 6;
-                unsigned int m = dmax;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    cnt += __shfl_xor(cnt, o, 64);
-                    m = max(m, (unsigned int)__shfl_xor(m, o, 64));
-                }
+                const unsigned int m = wave_max_u32(dmax);
+                // threshold counts are rare in noise: reduce them only if a lane has one
+                if (__builtin_amdgcn_ballot_w64(cnt != 0u) != 0ull) cnt = wave_sum_u32(cnt);
                 unsigned int* red_max = (unsigned int*)red_j;
                 if (lane == 0) {
                     red_cnt[wave] = cnt;

@@ -27,8 +27,18 @@ struct MaxSz {
     static constexpr size_t value = A > B ? A : B;
 };
 
+// Pass 1 keeps the occupancy its LDS allows for the wide FP32 tiles (8 waves
+// per SIMD: four 512-thread or two 1024-thread work-groups per CU, 64 VGPRs)
+// and for the FP64 256-thread tiles (4 waves, 128 VGPRs): it is bound by its
+// stores, which need many waves in flight.
+template <typename T, int NT>
+constexpr int pass1_min_waves() {
+    return sizeof(T) == 4 ? (NT >= 512 ? 8 : 1) : (NT == 256 ? 4 : 1);
+}
+
 template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
-__global__ void __launch_bounds__(NT) k_pass1(FilterArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass1_min_waves<T, NT>())))
+k_pass1(FilterArgs a) {
     using P = Pass1<T, PH, MODE, N1, N2, C, NT>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
@@ -182,9 +192,12 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
         fill(q, N1, N2, C, B, R2, XS);                                                                 \
         q.units = 0;                                                                                   \
         for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 ? 2 : 1); ++f) {                               \
-            q.fused = f == 1;                                                                          \
-            if (out && n < cap) out[n] = q;                                                            \
-            ++n;                                                                                       \
+            for (int pr = 0; pr < (pre0_fits(q) ? 2 : 1); ++pr) {                                      \
+                q.fused = f == 1;                                                                      \
+                q.pre0 = pr == 1;                                                                      \
+                if (out && n < cap) out[n] = q;                                                        \
+                ++n;                                                                                   \
+            }                                                                                          \
         }                                                                                              \
     }
     MF_SHAPES(MF_CAND)
@@ -228,6 +241,14 @@ Plan default_plan(int log2n, mf_precision prec) {
     // result).  Measured on MI355X (32768 uneven templates x 4 segments, FP32):
     // pass 1 1.495 -> 1.486 ms per 1024-unit launch; it is bound by its writes.
     p.prune1 = true;
+    // Pass 1 applies the row factor of pass 2's first stage (one complex
+    // product per element moves from the VALU-bound pass 2 to the store-bound
+    // pass 1; in FP32 the product is the same, so the results are bitwise
+    // equal).  Measured on MI355X, 32768 uneven templates x 4 segments: pass 2
+    // 1.680 -> 1.617 ms per 1024-unit launch (FP32), 2.093 -> 2.054 ms per
+    // 512 units (FP64), pass 1 unchanged; 1024 templates x 1 segment:
+    // 299k-305k -> 308k-310k units/s.
+    p.pre0 = pre0_fits(p);
     return p;
 }
 

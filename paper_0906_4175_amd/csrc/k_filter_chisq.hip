@@ -221,19 +221,41 @@ struct Pass2Band {
                         [[maybe_unused]] cx<T> base = trow[b * NS + s];
                         if constexpr (s == 0) {
                             if (from_inter) {
-                                const cx<T>* src = inter + (int64_t)(rb * B + b) * N2 + j;
+                                // 32-bit byte offsets from the unit's base: scalar-based loads
+                                const char* ib = (const char*)inter;
+                                const unsigned int o0 = (unsigned int)(((rb * B + b) * N2 + j) * (int)sizeof(cx<T>));
 #pragma unroll
-                                for (int r = 0; r < R; ++r) v[i][r] = src[r * PER_ROW];
+                                for (int r = 0; r < R; ++r)
+                                    v[i][r] = *(const cx<T>*)(ib + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>))));
                             } else {
 #pragma unroll
                                 for (int r = 0; r < R; ++r) v[i][r] = cx<T>{T(0), T(0)};
+                                // bins k < N/2 <= 2^21: 32-bit indices; a row wholly inside
+                                // the band needs no mask (uniform over the work-group)
+                                const char* qb = (const char*)q;
+                                const unsigned int span = (unsigned int)(e1 - e0);
                                 for (int k1 = r0; k1 <= r1; ++k1) {
                                     const cx<T> w = om[b * HALF + k1];
-                                    const int64_t kb = (int64_t)k1 * N2 + j;
+                                    const int kb = k1 * N2 + j;
+                                    const bool whole = (int64_t)k1 * N2 >= e0 && (int64_t)(k1 + 1) * N2 <= e1;
+                                    // groups of G loads issued together, so a wave waits for the
+                                    // cache once per group (the accumulators leave few registers)
+                                    constexpr int G = R >= 4 ? 4 : R;
 #pragma unroll
-                                    for (int r = 0; r < R; ++r) {
-                                        const int64_t k = kb + r * PER_ROW;
-                                        if (k >= e0 && k < e1) v[i][r] = v[i][r] + cmul(q[k], w);
+                                    for (int r0 = 0; r0 < R; r0 += G) {
+                                        cx<T> x[G];
+#pragma unroll
+                                        for (int g = 0; g < G; ++g)
+                                            x[g] = *(const cx<T>*)(qb + (unsigned int)(kb + (r0 + g) * PER_ROW) *
+                                                                            (unsigned int)sizeof(cx<T>));
+#pragma unroll
+                                        for (int g = 0; g < G; ++g) {
+                                            const int k = kb + (r0 + g) * PER_ROW;
+                                            if (!whole && (unsigned int)(k - (int)e0) >= span) x[g] = cx<T>{T(0), T(0)};
+                                            // v += x w as four fused multiply-adds
+                                            v[i][r0 + g].x = fma(x[g].x, w.x, fma(-x[g].y, w.y, v[i][r0 + g].x));
+                                            v[i][r0 + g].y = fma(x[g].x, w.y, fma(x[g].y, w.x, v[i][r0 + g].y));
+                                        }
                                     }
                                 }
                             }

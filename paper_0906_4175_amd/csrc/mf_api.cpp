@@ -245,19 +245,23 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     const int nt16 = clampt((long long)q.b2 * q.n2 / 16), nt8 = clampt((long long)q.b2 * q.n2 / 8);
     q.nt2 = plan[5] == nt8 ? nt8 : nt16;
     q.units = plan[6];
-    if ((plan[7] & ~15) || (plan[7] & 6) == 4)
+    if ((plan[7] & ~31) || (plan[7] & 6) == 4)
         return fail(MF_E_ARG,
                     "plan flags %d: bits 0 (pipelined step), 1 (split exchange), 2 (conflict-free layouts, with bit 1), "
-                    "3 (narrow-band pass 1)",
+                    "3 (narrow-band pass 1), 4 (pass 1 applies the first row factor)",
                     plan[7]);
     q.fused = (plan[7] & 1) != 0;
     q.xs = (plan[7] & 4) ? 2 : ((plan[7] & 2) ? 1 : 0);
     q.prune1 = (plan[7] & 8) != 0;
+    q.pre0 = (plan[7] & 16) != 0;
     if ((int64_t)q.n1 * q.n2 != grid->n || !mf::plan_supported(q, prec))
         return fail(MF_E_UNSUPPORTED,
                     "plan %dx%d c=%d b=%d (pass-2 threads %d, flags %d) is not built for this N/precision", q.n1, q.n2,
                     q.c1, q.b2, q.nt2, plan[7]);
     if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
+    if (q.pre0 && !mf::pre0_fits(q))
+        return fail(MF_E_UNSUPPORTED, "flag bit 4 needs the pass-1 columns (%d) to divide N2/R0 = %d", q.c1,
+                    q.n2 / mf::plan_r2(q));
     if (q.fused && (q.nt1 != q.nt2 || q.nt2 != nt16))
         return fail(MF_E_UNSUPPORTED, "pipelined step needs equal work-group sizes and radix-16 row stages");
     mf::g_plans[{l, prec == MF_FP64}] = q;
@@ -418,6 +422,7 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
     a.ev_log2w = ev_log2w;
     a.tw2 = ws + L.off_tw2;
     a.prune1 = p.prune1 ? 1 : 0;
+    a.pre0_r0 = p.pre0 && mf::pre0_fits(p) ? mf::plan_r2(p) : 0;
 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);

@@ -124,6 +124,38 @@ __device__ __forceinline__ void butterfly_diag(cx<T> e, cx<T> a, cx<T>& lo, cx<T
     hi = cx<T>{fma(sx, -h, e.x), fma(sy, -h, e.y)};
 }
 
+// Butterfly (e + w a, e - w a) with w = e^{2 pi i q / 16}, q odd and q < 8:
+// w a = k (y.x, y.y) with k the larger of |cos|, |sin| (signed) and y formed by
+// two fused multiply-adds with the ratio of the smaller to the larger
+// (tan or cot of pi/8 in magnitude), so each output component is one more
+// fused multiply-add: 6 operations instead of 8.
+template <int Q, typename T>
+__device__ __forceinline__ void butterfly_odd(cx<T> e, cx<T> a, cx<T>& lo, cx<T>& hi) {
+    static_assert(Q == 1 || Q == 3 || Q == 5 || Q == 7, "odd sixteenth roots in the upper half plane");
+    constexpr T t8 = T(0.41421356237309505);  // tan(pi/8)
+    constexpr T c8 = T(0.92387953251128674);  // cos(pi/8)
+    T yx, yy, k;
+    if constexpr (Q == 1) {  // cos = c8, sin = t8 c8: w a = c8 (a.x - t8 a.y, a.y + t8 a.x)
+        yx = fma(-t8, a.y, a.x);
+        yy = fma(t8, a.x, a.y);
+        k = c8;
+    } else if constexpr (Q == 3) {  // cos = t8 c8, sin = c8: w a = c8 (t8 a.x - a.y, a.x + t8 a.y)
+        yx = fma(t8, a.x, -a.y);
+        yy = fma(t8, a.y, a.x);
+        k = c8;
+    } else if constexpr (Q == 5) {  // cos = -t8 c8, sin = c8: w a = c8 (-t8 a.x - a.y, a.x - t8 a.y)
+        yx = fma(-t8, a.x, -a.y);
+        yy = fma(-t8, a.y, a.x);
+        k = c8;
+    } else {  // Q == 7: cos = -c8, sin = t8 c8: w a = c8 (-a.x - t8 a.y, t8 a.x - a.y)
+        yx = fma(-t8, a.y, -a.x);
+        yy = fma(t8, a.x, -a.y);
+        k = c8;
+    }
+    lo = cx<T>{fma(yx, k, e.x), fma(yy, k, e.y)};
+    hi = cx<T>{fma(yx, -k, e.x), fma(yy, -k, e.y)};
+}
+
 template <int R, typename T>
 struct IDft {
     template <int U>
@@ -132,6 +164,8 @@ struct IDft {
             constexpr int q = (U * 16 / R) % 16;
             if constexpr (q == 2 || q == 6 || q == 10 || q == 14) {
                 butterfly_diag<q, T>(e[U], o[U], v[U], v[U + R / 2]);
+            } else if constexpr (q == 1 || q == 3 || q == 5 || q == 7) {
+                butterfly_odd<q, T>(e[U], o[U], v[U], v[U + R / 2]);
             } else {
                 cx<T> t = rot<U, R>(o[U]);
                 v[U] = e[U] + t;
@@ -174,6 +208,31 @@ __host__ __device__ constexpr int ilog2(long long x) {
     int r = 0;
     while ((1LL << r) < x) ++r;
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-wide reductions of a 32-bit value (all 64 lanes active): four DPP
+// steps reduce each row of 16 lanes (swap neighbours, swap pairs, mirror the
+// half-row, mirror the row), then the four row results are read into scalar
+// registers.  The result is wave-uniform.
+// ---------------------------------------------------------------------------
+template <typename Op>
+__device__ __forceinline__ unsigned int wave_reduce_u32(unsigned int v, Op op) {
+    v = op(v, (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    v = op(v, (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    v = op(v, (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    v = op(v, (unsigned int)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xf, 0xf, false));  // row_mirror
+    const unsigned int r0 = (unsigned int)__builtin_amdgcn_readlane((int)v, 0);
+    const unsigned int r1 = (unsigned int)__builtin_amdgcn_readlane((int)v, 16);
+    const unsigned int r2 = (unsigned int)__builtin_amdgcn_readlane((int)v, 32);
+    const unsigned int r3 = (unsigned int)__builtin_amdgcn_readlane((int)v, 48);
+    return op(op(r0, r1), op(r2, r3));
+}
+__device__ __forceinline__ unsigned int wave_max_u32(unsigned int v) {
+    return wave_reduce_u32(v, [](unsigned int a, unsigned int b) { return a > b ? a : b; });
+}
+__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v) {
+    return wave_reduce_u32(v, [](unsigned int a, unsigned int b) { return a + b; });
 }
 
 // ---------------------------------------------------------------------------

@@ -29,11 +29,16 @@ struct Plan {
     int xs;          // pass-2 exchange: 0 complex values, 1 real and imaginary parts one
                      // after the other (half the LDS), 2 as 1 with bank-conflict-free layouts
     bool prune1;     // pass 1 skips the stage-0 transform where a band has only rows k1 < N1/16
+    bool pre0;       // pass 1 applies the row factor of pass 2's first stage (see FilterArgs::pre0_r0)
 };
 // plan flags (last entry of the public plan array)
 inline int plan_flags(const Plan& p) {
-    return (p.fused ? 1 : 0) | (p.xs >= 1 ? 2 : 0) | (p.xs == 2 ? 4 : 0) | (p.prune1 ? 8 : 0);
+    return (p.fused ? 1 : 0) | (p.xs >= 1 ? 2 : 0) | (p.xs == 2 ? 4 : 0) | (p.prune1 ? 8 : 0) | (p.pre0 ? 16 : 0);
 }
+// largest radix of the pass-2 stages (16 or 8), from the pass-2 threads
+inline int plan_r2(const Plan& p) { return p.nt2 == p.b2 * p.n2 / 8 ? 8 : 16; }
+// pre0 needs every pass-1 work-group inside one block of N2/R0 columns
+inline bool pre0_fits(const Plan& p) { return (p.n2 / plan_r2(p)) % p.c1 == 0; }
 
 Plan default_plan(int log2n, mf_precision prec);
 bool plan_supported(const Plan& p, mf_precision prec);
@@ -87,6 +92,10 @@ struct FilterArgs {
     int32_t ev_log2w;
     const void* tw2;              // [kTw2Radix - 1][kTw2Span] last-stage factors (see pass2_uses_tw2)
     int32_t prune1;               // pass 1 skips the stage-0 transform of narrow bands (plan flag bit 3)
+    // pre0_r0 > 0 (plan flag bit 4): pass 1 multiplies its output Y[j1][k2] by
+    // e^{2 pi i j1 floor(k2 / (N2/R0)) / (N1 R0)}, the factor pass 2's first
+    // stage (radix R0 = pre0_r0) would apply to that input, and pass 2 skips it
+    int32_t pre0_r0;
 };
 
 // Workspace carve-up of mf_filter_chisq (band mode).

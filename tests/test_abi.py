@@ -171,13 +171,22 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert lib.mf_filter_plan(C.byref(g), 1, out) == 0
     assert list(out)[:4] == [256, 4096, 32, 1]
     # flags: bit 0 pipelined step, bit 1 split pass-2 exchange, bit 2 its conflict-free
-    # layouts, bit 3 narrow-band pass 1 (the 2^20 FP32 default: 2 | 4 | 8)
-    assert out[7] == 14
+    # layouts, bit 3 narrow-band pass 1, bit 4 first row factor in pass 1
+    # (the 2^20 FP32 default: 2 | 4 | 8 | 16)
+    assert out[7] == 30
     flags = {(tuple(buf[8 * i: 8 * i + 6]), buf[8 * i + 7]) for i in range(n)}
     for f in (0, 1, 2, 3):  # separate or pipelined launches, complex or split exchange
         assert ((256, 4096, 16, 1, 256, 256), f) in flags
-    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 16)  # unknown flag bit
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 32)  # unknown flag bit
     assert lib.mf_set_plan(C.byref(g), 1, bad) == -1
+    # bit 4 (pass 1 applies the first row factor) needs the pass-1 columns to divide N2/R0
+    good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 16 | 14)
+    assert lib.mf_set_plan(C.byref(g), 1, good) == 0
+    assert lib.mf_filter_plan(C.byref(g), 1, out) == 0 and out[7] == 30
+    g10 = _grid(n=1 << 10, fs=256.0, f_low=20.0)
+    bad = (C.c_int32 * 8)(32, 32, 16, 32, 64, 64, 4, 16)  # 16 columns per tile, N2/R0 = 2
+    assert lib.mf_set_plan(C.byref(g10), 1, bad) == -6
+    assert b"bit 4" in lib.mf_last_error()
     bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 4)  # conflict-free layouts without the split exchange
     assert lib.mf_set_plan(C.byref(g), 1, bad) == -1
     for f in (6, 7, 14):  # conflict-free split exchange, with the pipelined step, with the narrow-band pass 1
@@ -195,14 +204,14 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert lib.mf_set_plan(C.byref(g), 1, None) == 0
     g22 = _grid(n=1 << 22)
     assert lib.mf_filter_plan(C.byref(g22), 1, out) == 0
-    assert list(out)[:4] == [1024, 4096, 16, 1] and out[7] == 10
+    assert list(out)[:4] == [1024, 4096, 16, 1] and out[7] == 26
 
 
 @pytest.mark.parametrize("n, prec, shape, threads, units, flags", [
-    (1 << 20, 1, [256, 4096, 32, 1], [512, 256], 1024, 14),   # FP32 (FP64 phase): 8 GiB of intermediates
-    (1 << 20, 2, [256, 4096, 32, 1], [512, 256], 1024, 14),   # FP32 phase: same plan class
-    (1 << 20, 0, [256, 4096, 16, 1], [256, 256], 512, 10),    # FP64: padded split exchange
-    (1 << 22, 1, [1024, 4096, 16, 1], [1024, 256], 256, 10),  # 4 x 2^20 samples
+    (1 << 20, 1, [256, 4096, 32, 1], [512, 256], 1024, 30),   # FP32 (FP64 phase): 8 GiB of intermediates
+    (1 << 20, 2, [256, 4096, 32, 1], [512, 256], 1024, 30),   # FP32 phase: same plan class
+    (1 << 20, 0, [256, 4096, 16, 1], [256, 256], 512, 26),    # FP64: padded split exchange
+    (1 << 22, 1, [1024, 4096, 16, 1], [1024, 256], 256, 26),  # 4 x 2^20 samples
 ])
 def test_default_plans(lib, n, prec, shape, threads, units, flags):
     g = _grid(n=n)
@@ -210,7 +219,7 @@ def test_default_plans(lib, n, prec, shape, threads, units, flags):
     out = (C.c_int32 * 8)()
     assert lib.mf_filter_plan(C.byref(g), prec, out) == 0
     assert list(out)[:4] == shape and list(out)[4:6] == threads and out[6] == units
-    assert out[7] == flags  # separate launches, split pass-2 exchange, narrow-band pass 1
+    assert out[7] == flags  # separate launches, split pass-2 exchange, narrow-band pass 1, first row factor in pass 1
 
 
 def test_tune_cache_corrupt_and_foreign(tmp_path):
