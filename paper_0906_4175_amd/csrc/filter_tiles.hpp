@@ -112,7 +112,10 @@ __device__ __forceinline__ int digit_weight_rt(int st) {
 // [k1][k2]) and transforms only its part inside one chi^2 band.
 // Output: Y[j1][k2] = sum_k1 q[N2 k1 + k2] e^{2 pi i j1 k1 / N1}.
 // ---------------------------------------------------------------------------
-enum Pass1Mode { P1_PRODUCT = 0, P1_RAW = 1, P1_BAND = 2 };
+// P1_PRODUCT_PRE is P1_PRODUCT that also applies the row factor of pass 2's
+// first stage to its output (FilterArgs::pre0_r0); a separate instantiation,
+// so the plain product keeps its register budget.
+enum Pass1Mode { P1_PRODUCT = 0, P1_RAW = 1, P1_BAND = 2, P1_PRODUCT_PRE = 3 };
 
 template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
 struct Pass1 {
@@ -140,12 +143,13 @@ struct Pass1 {
     // heavier than about 17 M_sun at N1 = 256): every stage-0 butterfly has a
     // single non-zero input, so its 16 outputs all equal that input and stage 1
     // reads the products directly (no stage-0 transform, one LDS value per row).
-    static constexpr bool NARROW_OK = MODE == P1_PRODUCT && XS && NS == 2 && radix_at(N1, 0) == 16 &&
+    static constexpr bool PRODUCT = MODE == P1_PRODUCT || MODE == P1_PRODUCT_PRE;
+    static constexpr bool NARROW_OK = PRODUCT && XS && NS == 2 && radix_at(N1, 0) == 16 &&
                                       radix_at(N1, 1) == 16 && C * N1 / 16 == NT;
     static constexpr size_t BUF_BYTES = (size_t)N1 * C * (XS ? sizeof(T) : sizeof(cx<T>));
     // PRE (product mode, FilterArgs::pre0_r0 > 0): the factor pass 2's first
     // stage would apply to this tile's columns, one per output row j1
-    static constexpr int PRE = MODE == P1_PRODUCT ? N1 : 0;
+    static constexpr int PRE = MODE == P1_PRODUCT_PRE ? N1 : 0;
     static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1 + PRE) * sizeof(cx<T>);
 
     __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
@@ -192,7 +196,7 @@ struct Pass1 {
         [[maybe_unused]] const bool narrow = NARROW_OK && a.prune1 != 0 && khi < (N1 / 16) * N2;
         // PRE: row j1 of this tile's columns k2 (all in one block of N2/R0, so
         // rr = floor(k2 / (N2/R0)) is the tile's) takes e^{2 pi i j1 rr / (N1 R0)}
-        [[maybe_unused]] const bool pre = PRE > 0 && a.pre0_r0 > 0;
+        [[maybe_unused]] constexpr bool pre = PRE > 0;
         auto fill_pre = [&]() {
             if constexpr (PRE > 0) {
                 if (pre) {

@@ -192,7 +192,7 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
         fill(q, N1, N2, C, B, R2, XS);                                                                 \
         q.units = 0;                                                                                   \
         for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 ? 2 : 1); ++f) {                               \
-            for (int pr = 0; pr < (pre0_fits(q) ? 2 : 1); ++pr) {                                      \
+            for (int pr = 0; pr < (pre0_fits(q) && f == 0 ? 2 : 1); ++pr) {                            \
                 q.fused = f == 1;                                                                      \
                 q.pre0 = pr == 1;                                                                      \
                 if (out && n < cap) out[n] = q;                                                        \
@@ -301,6 +301,11 @@ hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const Filter
 #define MF_P1(T, N1, N2, C, B, R2, XS)                                                                          \
     if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {    \
         if (raw) return run_pass1<T, 0, P1_RAW, N1, N2, C>(a, s);                                              \
+        if (a.pre0_r0 > 0) {                                                                                   \
+            if (std::is_same<T, float>::value && prec == MF_FP32)                                              \
+                return run_pass1<float, 1, P1_PRODUCT_PRE, N1, N2, C>(a, s);                                   \
+            return run_pass1<T, 0, P1_PRODUCT_PRE, N1, N2, C>(a, s);                                           \
+        }                                                                                                      \
         if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
             return run_pass1<float, 1, P1_PRODUCT, N1, N2, C>(a, s);                                           \
         return run_pass1<T, 0, P1_PRODUCT, N1, N2, C>(a, s);                                                   \

@@ -259,6 +259,8 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
                     "plan %dx%d c=%d b=%d (pass-2 threads %d, flags %d) is not built for this N/precision", q.n1, q.n2,
                     q.c1, q.b2, q.nt2, plan[7]);
     if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
+    if (q.pre0 && q.fused)
+        return fail(MF_E_UNSUPPORTED, "flag bit 4 (pass 1 applies the first row factor) is not built for the pipelined step");
     if (q.pre0 && !mf::pre0_fits(q))
         return fail(MF_E_UNSUPPORTED, "flag bit 4 needs the pass-1 columns (%d) to divide N2/R0 = %d", q.c1,
                     q.n2 / mf::plan_r2(q));
@@ -422,7 +424,7 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
     a.ev_log2w = ev_log2w;
     a.tw2 = ws + L.off_tw2;
     a.prune1 = p.prune1 ? 1 : 0;
-    a.pre0_r0 = p.pre0 && mf::pre0_fits(p) ? mf::plan_r2(p) : 0;
+    a.pre0_r0 = p.pre0 && !p.fused && mf::pre0_fits(p) ? mf::plan_r2(p) : 0;
 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);

@@ -183,6 +183,8 @@ def test_plan_candidates_and_set_plan_validation(lib):
     good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 16 | 14)
     assert lib.mf_set_plan(C.byref(g), 1, good) == 0
     assert lib.mf_filter_plan(C.byref(g), 1, out) == 0 and out[7] == 30
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 16 | 1)  # with the pipelined step
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
     g10 = _grid(n=1 << 10, fs=256.0, f_low=20.0)
     bad = (C.c_int32 * 8)(32, 32, 16, 32, 64, 64, 4, 16)  # 16 columns per tile, N2/R0 = 2
     assert lib.mf_set_plan(C.byref(g10), 1, bad) == -6
