@@ -21,7 +21,8 @@
  *
  * Conventions for every call:
  *  - Pointers named *_dev are device pointers; *_host are host pointers.
- *    The caller owns every buffer.  The library allocates no device memory.
+ *    The caller owns every buffer.  The library calls no device allocator
+ *    (mf_filter_noalloc works in a static device array of the library).
  *  - Complex arrays are interleaved (re, im) pairs: complex64 = 2 x float,
  *    complex128 = 2 x double.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Hot calls only
