@@ -17,6 +17,9 @@ struct __align__(2 * sizeof(T)) cx {
 
 template <typename T>
 __device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
+// two-element vector of T (one 8- or 16-byte access), for the non-temporal loads and stores
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
