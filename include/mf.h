@@ -353,9 +353,11 @@ mf_status mf_chisq_events(const mf_grid* grid, const void* bank_dev, int64_t n_t
 
 /*
  * mf_filter_chisq_workspace_bytes -- device workspace mf_filter_chisq needs:
- * the weighted data, the band table, and per batch of units the template x
- * weight product [N/2] and one intermediate [N], plus peak partials.  0 for
- * invalid arguments (no band-mode plan, p_bands outside [2, 64]).
+ * the weighted data, the band table, and per unit of a batch the template x
+ * weight product of the bands that are not transformed whole (at most
+ * N/2 + p_bands (N2 + 16) values, N2 the plan's row length) and one
+ * intermediate [N], plus peak partials.  0 for invalid arguments (no
+ * band-mode plan, p_bands outside [2, 64]).
  */
 size_t mf_filter_chisq_workspace_bytes(const mf_grid* grid, mf_precision prec, int64_t n_tmpl,
                                        int64_t n_seg, int32_t p_bands);

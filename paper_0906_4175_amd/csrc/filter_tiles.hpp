@@ -108,14 +108,30 @@ __device__ __forceinline__ int digit_weight_rt(int st) {
 // Pass 1 tile: C adjacent columns k2 of one unit.
 // PH: 0 = FP64 phase, 1 = FP32 phase.  MODE: P1_PRODUCT transforms the
 // template x weight product; P1_RAW a full N-point spectrum (diagnostic
-// inverse DFT); P1_BAND also stores the product q (rows k1 < N1/2, layout
-// [k1][k2]) and transforms only its part inside one chi^2 band.
+// inverse DFT); P1_BAND transforms only the product's part inside one chi^2
+// band and stores the other bands' parts in their slots (below).
 // Output: Y[j1][k2] = sum_k1 q[N2 k1 + k2] e^{2 pi i j1 k1 / N1}.
 // ---------------------------------------------------------------------------
 // P1_PRODUCT_PRE is P1_PRODUCT that also applies the row factor of pass 2's
 // first stage to its output (FilterArgs::pre0_r0); a separate instantiation,
 // so the plain product keeps its register budget.
+//
+// chi^2 band mode: every non-empty band l but the transformed one keeps its
+// product in a slot, a copy of the bins [s_l, s_l + n_l N2) with s_l = e_l
+// rounded down to a multiple of kSlotAlign and n_l = ceil((e_{l+1} - s_l) / N2),
+// zero outside the band.  The band table of a template holds the edges
+// e_0..e_p, the transformed band's index and the slot starts (prefix sums of
+// n_l N2, p + 1 entries); a unit's slots take at most band_slot_stride
+// complex values.
 enum Pass1Mode { P1_PRODUCT = 0, P1_RAW = 1, P1_BAND = 2, P1_PRODUCT_PRE = 3 };
+
+constexpr int kSlotAlign = 16;
+constexpr int kMaxBands = 64;
+__host__ __device__ constexpr int band_tab_stride(int p) { return 2 * p + 3; }
+// sum_l n_l N2 <= sum_l (e_{l+1} - e_l + kSlotAlign - 1 + N2 - 1) <= n/2 + p (N2 + kSlotAlign)
+__host__ __device__ constexpr int64_t band_slot_stride(int64_t n, int n2, int p) {
+    return n / 2 + (int64_t)p * (n2 + kSlotAlign);
+}
 
 template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
 struct Pass1 {
@@ -150,7 +166,9 @@ struct Pass1 {
     // PRE (product mode, FilterArgs::pre0_r0 > 0): the factor pass 2's first
     // stage would apply to this tile's columns, one per output row j1
     static constexpr int PRE = MODE == P1_PRODUCT_PRE ? N1 : 0;
-    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1 + PRE) * sizeof(cx<T>);
+    // P1_BAND: the template's band edges and slot starts
+    static constexpr int BANDI = MODE == P1_BAND ? 2 * (kMaxBands + 1) : 0;
+    static constexpr size_t SMEM = BUF_BYTES + (size_t)(TW + T1 + PRE) * sizeof(cx<T>) + (size_t)BANDI * sizeof(int);
 
     __device__ static void run(const FilterArgs& a, char* smem, int tile, int64_t ul) {
         cx<T>* buf = (cx<T>*)smem;
@@ -158,6 +176,8 @@ struct Pass1 {
         cx<T>* tw = (cx<T>*)(smem + BUF_BYTES);
         cx<T>* t1 = tw + TW;  // [k][r]
         cx<T>* tpre = t1 + T1;  // PRE: [j1]
+        [[maybe_unused]] int* bedge = (int*)(tpre + PRE);  // P1_BAND: e_0..e_p
+        [[maybe_unused]] int* bslot = bedge + kMaxBands + 1;  // P1_BAND: slot starts
         [[maybe_unused]] cx<T> carry[XS ? EPT : 1];
         const int tid = threadIdx.x;
         const int k2_0 = tile * C;
@@ -169,7 +189,8 @@ struct Pass1 {
         const cx<T>* w = nullptr;
         const cx<T>* qin = nullptr;
         int blo = 0, bhi = 0;      // P1_BAND: the transformed band [blo, bhi)
-        cx<T>* qout = nullptr;     // P1_BAND: product rows [k1][k2], k1 < N1/2
+        cx<T>* slots = nullptr;    // P1_BAND: this unit's band slots
+        [[maybe_unused]] const int nb = a.p_bands;
         if constexpr (RAW) {
             qin = (const cx<T>*)a.raw_in + u * N;
         } else {
@@ -181,11 +202,29 @@ struct Pass1 {
             khi = e.k_hi;
             w = (const cx<T>*)a.wgt + s * (N / 2 + 1);
             if constexpr (MODE == P1_BAND) {
-                const int32_t* tab = a.band_tab + t * (a.p_bands + 2);
-                const int wb = tab[a.p_bands + 1];
+                const int32_t* tab = a.band_tab + t * band_tab_stride(nb);
+                const int wb = tab[nb + 1];
                 blo = tab[wb];
                 bhi = tab[wb + 1];
-                qout = (cx<T>*)a.qbuf + ul * (N / 2);
+                slots = (cx<T>*)a.qbuf + ul * band_slot_stride(N, N2, nb);
+                for (int q = tid; q <= nb; q += NT) {
+                    bedge[q] = tab[q];
+                    bslot[q] = tab[nb + 2 + q];
+                }
+                __syncthreads();
+                // the slot bins outside their band: the head [s_l, e_l) lies in row
+                // e_l / N2, the tail [e_{l+1}, s_l + n_l N2) (shorter than N2) in rows
+                // e_{l+1} / N2 and the next; this tile writes the zeros of its columns
+                for (int q = tid; q < nb * 3 * C; q += NT) {
+                    const int l = q / (3 * C), d = (q / C) % 3, c = q % C;
+                    const int sb0 = bslot[l], len = bslot[l + 1] - sb0;
+                    const int e0 = bedge[l], e1 = bedge[l + 1];
+                    const int sl = e0 & ~(kSlotAlign - 1);
+                    const int row = d == 0 ? e0 / N2 : e1 / N2 + d - 1;
+                    const int k = row * N2 + k2_0 + c;
+                    const bool pad = d == 0 ? (k >= sl && k < e0) : (k >= e1 && k < sl + len);
+                    if (len > 0 && pad) slots[sb0 + (k - sl)] = cx<T>{T(0), T(0)};
+                }
             }
             if (tile == 0 && tid == 0 && a.keys != nullptr) {
                 a.keys[u] = 0ull;
@@ -292,8 +331,18 @@ struct Pass1 {
                                         v[i][r] = cmul(rotor, wk[r]);
                                     }
                                     if constexpr (MODE == P1_BAND) {
-                                        qout[k] = v[i][r];
-                                        if (k < blo || k >= bhi) v[i][r] = cx<T>{T(0), T(0)};
+                                        if (k < blo || k >= bhi) {
+                                            if (k >= bedge[0] && k < bedge[nb]) {
+                                                // the band of k: e_l <= k < e_{l+1} (bisection, e_0 <= k < e_p)
+                                                int lo = 0, hi = nb;
+                                                while (hi - lo > 1) {
+                                                    const int mid = (lo + hi) >> 1;
+                                                    if (bedge[mid] <= k) lo = mid; else hi = mid;
+                                                }
+                                                slots[bslot[lo] + (k - (bedge[lo] & ~(kSlotAlign - 1)))] = v[i][r];
+                                            }
+                                            v[i][r] = cx<T>{T(0), T(0)};
+                                        }
                                     }
                                 }
                             }

@@ -8,15 +8,19 @@
 // DFT of the matched filter (bins k = N2 k1 + k2, times j = j1 + N1 j2):
 //
 //  * The bands are contiguous in k and, except the widest, span only a few
-//    rows k1.  Pass 1 writes the template x weight product q (rows k1 < N1/2,
-//    once) and transforms only the widest band; its column-transform output
-//    goes to the intermediate as in the plain filter.
-//  * Pass 2 rebuilds row j1 of every other band directly from the few q rows
-//    it touches, Y_l[j1][k2] = sum_{k1 in band l} q[k1][k2] e^{2 pi i j1 k1/N1},
-//    runs the p row transforms, accumulates z and sum_l |z_l|^2 in registers
-//    and reduces |z|^2 (peak, threshold count, series) together with chi^2.
+//    thousand bins.  Pass 1 transforms only the widest band (its column
+//    transform goes to the intermediate as in the plain filter) and copies
+//    the template x weight product q of every other band l into a slot: the
+//    n_l rows of N2 bins from s_l (e_l rounded down to a multiple of 16),
+//    zero outside the band.
+//  * Pass 2 rebuilds row j1 of every other band from its slot,
+//    Y_l[j1][k2] = sum_m q[s_l + m N2 + k2] e^{2 pi i j1 m / N1} (mostly a
+//    single row, so no products), runs the p row transforms, accumulates
+//    z = sum_l e^{2 pi i s_l j / N} (transform of slot l) and sum_l |z_l|^2 in
+//    registers and reduces |z|^2 (peak, threshold count, series) together
+//    with chi^2.
 //
-// Per unit this moves the product (written once, re-read from cache), one
+// Per unit this moves the slots (written once, re-read from cache), one
 // intermediate and the weights instead of p intermediates.
 #include "filter_tiles.hpp"
 
@@ -38,19 +42,23 @@ struct PartialChi {
 // Band table of one template: e_0 = k_lo < e_1 <= ... <= e_p = k_hi + 1 with
 // e_l = min{k : P[k-1] - P[k_lo-1] >= l/p (P[k_hi] - P[k_lo-1])} (a bin
 // belongs to the band in which the sigma^2 sum before it falls), then the
-// index of the band spanning the most rows of N2 bins.
+// index of the band with the most slot rows n_l (the one pass 1 transforms),
+// then the slot starts sum_{l' < l} n_l' N2 (n_l = 0 for it and for empty bands).
 __global__ void __launch_bounds__(64) k_band_table(int64_t n, int n2, const mf_bank_entry* bank, const double* P,
                                                    int p, int32_t* tab) {
-    __shared__ int64_t edge[65];
+    __shared__ int64_t edge[kMaxBands + 1];
     const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
     const mf_bank_entry e = bank[t];
     const int64_t klo = e.k_lo, khi = e.k_hi;
-    int32_t* row = tab + t * (p + 2);
+    int32_t* row = tab + t * band_tab_stride(p);
     const bool valid = klo >= 1 && khi >= klo && khi <= n / 2 - 1;
     if (!valid) {
-        // empty bands: every bin stays untouched and the unit outputs zero
-        for (int l = tid; l <= p; l += 64) row[l] = 1;
+        // empty bands and slots: every bin stays untouched and the unit outputs zero
+        for (int l = tid; l <= p; l += 64) {
+            row[l] = 1;
+            row[p + 2 + l] = 0;
+        }
         if (tid == 0) row[p + 1] = 0;
         return;
     }
@@ -71,16 +79,26 @@ __global__ void __launch_bounds__(64) k_band_table(int64_t n, int n2, const mf_b
     __syncthreads();
     for (int l = tid; l <= p; l += 64) row[l] = (int32_t)edge[l];
     if (tid == 0) {
+        auto slot_rows = [&](int l) -> int64_t {
+            const int64_t sl = edge[l] & ~(int64_t)(kSlotAlign - 1);
+            return edge[l + 1] > edge[l] ? (edge[l + 1] - sl + n2 - 1) / n2 : 0;
+        };
         int wide = 0;
         int64_t best = -1;
         for (int l = 0; l < p; ++l) {
-            const int64_t rows = edge[l + 1] > edge[l] ? (edge[l + 1] - 1) / n2 - edge[l] / n2 + 1 : 0;
+            const int64_t rows = slot_rows(l);
             if (rows > best) {
                 best = rows;
                 wide = l;
             }
         }
         row[p + 1] = wide;
+        int64_t acc = 0;
+        for (int l = 0; l < p; ++l) {
+            row[p + 2 + l] = (int32_t)acc;
+            if (l != wide) acc += slot_rows(l) * n2;
+        }
+        row[2 * p + 2] = (int32_t)acc;
     }
 }
 
@@ -121,6 +139,7 @@ struct Pass2Band {
     // exchanges use the bank-conflict-free layouts of the plain pass 2 (on
     // complex values, where a half-wave must touch 32 distinct 8-byte slots).
     static constexpr bool CF = N2 == 4096 && MAXR == 16 && B == 1 && NT == 256;
+    static_assert(kSlotAlign % RL == 0, "slot starts make the band factor uniform over a butterfly");
     static_assert(!CF || PN2 >= kCfSlots, "conflict-free layout slots");
 
     template <int STEP>
@@ -148,10 +167,11 @@ struct Pass2Band {
         const int64_t u = a.unit0 + ul;
         const int64_t t = u % a.n_tmpl;
         const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
-        const cx<T>* q = (const cx<T>*)a.qbuf + ul * (N / 2);
         const int P = a.p_bands;
-        const int32_t* tab = a.band_tab + t * (P + 2);
+        const int32_t* tab = a.band_tab + t * band_tab_stride(P);
         const int wb = tab[P + 1];
+        const int32_t* slot0 = tab + P + 2;
+        const cx<T>* slots = (const cx<T>*)a.qbuf + ul * band_slot_stride(N, N2, P);
 
         if (tid < B * NS) {
             const int b = tid / NS, st = tid % NS;
@@ -203,7 +223,9 @@ struct Pass2Band {
             const int64_t e0 = tab[l], e1 = tab[l + 1];
             if (e0 >= e1) continue;  // empty band (uniform over the work-group)
             const bool from_inter = l == wb;
-            const int r0 = (int)(e0 / N2), r1 = (int)((e1 - 1) / N2);  // r1 < N1/2
+            const int sb = slot0[l];
+            const int nrow = (slot0[l + 1] - sb) / N2;
+            const unsigned int sl = from_inter ? 0u : (unsigned int)e0 & ~(unsigned int)(kSlotAlign - 1);
             static_for<0, NS>([&](auto S_) {
                 constexpr int s = decltype(S_)::value;
                 constexpr int R = radix_at(N2, s, MAXR);
@@ -228,16 +250,16 @@ struct Pass2Band {
                                 for (int r = 0; r < R; ++r)
                                     v[i][r] = *(const cx<T>*)(ib + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>))));
                             } else {
+                                // slot row m holds the bins s_l + m N2 + k2 (zero outside the
+                                // band): Y[k2] = sum_m slot[m N2 + k2] e^{2 pi i j1 m / N1}
+                                const char* sp = (const char*)(slots + sb);
+                                const unsigned int o0 = (unsigned int)(j * (int)sizeof(cx<T>));
 #pragma unroll
-                                for (int r = 0; r < R; ++r) v[i][r] = cx<T>{T(0), T(0)};
-                                // bins k < N/2 <= 2^21: 32-bit indices; a row wholly inside
-                                // the band needs no mask (uniform over the work-group)
-                                const char* qb = (const char*)q;
-                                const unsigned int span = (unsigned int)(e1 - e0);
-                                for (int k1 = r0; k1 <= r1; ++k1) {
-                                    const cx<T> w = om[b * HALF + k1];
-                                    const int kb = k1 * N2 + j;
-                                    const bool whole = (int64_t)k1 * N2 >= e0 && (int64_t)(k1 + 1) * N2 <= e1;
+                                for (int r = 0; r < R; ++r)
+                                    v[i][r] = *(const cx<T>*)(sp + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>))));
+                                for (int m = 1; m < nrow; ++m) {
+                                    const cx<T> w = om[b * HALF + m];
+                                    const unsigned int om0 = o0 + (unsigned int)(m * N2 * (int)sizeof(cx<T>));
                                     // groups of G loads issued together, so a wave waits for the
                                     // cache once per group (the accumulators leave few registers)
                                     constexpr int G = R >= 4 ? 4 : R;
@@ -246,12 +268,10 @@ struct Pass2Band {
                                         cx<T> x[G];
 #pragma unroll
                                         for (int g = 0; g < G; ++g)
-                                            x[g] = *(const cx<T>*)(qb + (unsigned int)(kb + (r0 + g) * PER_ROW) *
-                                                                            (unsigned int)sizeof(cx<T>));
+                                            x[g] = *(const cx<T>*)(sp + (om0 + (unsigned int)((r0 + g) * PER_ROW *
+                                                                                               (int)sizeof(cx<T>))));
 #pragma unroll
                                         for (int g = 0; g < G; ++g) {
-                                            const int k = kb + (r0 + g) * PER_ROW;
-                                            if (!whole && (unsigned int)(k - (int)e0) >= span) x[g] = cx<T>{T(0), T(0)};
                                             // v += x w as four fused multiply-adds
                                             v[i][r0 + g].x = fma(x[g].x, w.x, fma(-x[g].y, w.y, v[i][r0 + g].x));
                                             v[i][r0 + g].y = fma(x[g].x, w.y, fma(x[g].y, w.x, v[i][r0 + g].y));
@@ -293,10 +313,21 @@ struct Pass2Band {
                 if constexpr (s == NS - 1) {
 #pragma unroll
                     for (int i = 0; i < BPT; ++i) {
+                        // z_l(j) is e^{2 pi i s_l j / N} times the transform of the slot
+                        // (s_l = 0 for the transformed band); with j = j1 + N1 (j' + NSPAN r)
+                        // the factor does not depend on r (s_l N1 NSPAN = (s_l / R) N): one
+                        // per butterfly
+                        const int bf = tid + i * NT;
+                        const int jj = bf % PER_ROW;
+                        const int b = bf / PER_ROW;
+                        const unsigned int m = (sl * (unsigned int)(rb * B + b + N1 * jj)) & (unsigned int)(N - 1);
+                        const cx<T> ph = root_of_unity((T)(int)m / (T)N);
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
-                            accz[i][r] = accz[i][r] + v[i][r];
-                            accq[i][r] += norm2(v[i][r]);
+                            const cx<T> y = v[i][r];
+                            accz[i][r].x = fma(y.x, ph.x, fma(-y.y, ph.y, accz[i][r].x));
+                            accz[i][r].y = fma(y.x, ph.y, fma(y.y, ph.x, accz[i][r].y));
+                            accq[i][r] += norm2(y);
                         }
                     }
                 } else {
@@ -536,9 +567,9 @@ BandLayout band_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tm
     L.off_w = off;
     off = align256b(off + (size_t)n_seg * (size_t)(n / 2 + 1) * cx_bytes(prec));
     L.off_tab = off;
-    off = align256b(off + (size_t)n_tmpl * (size_t)(p_bands + 2) * sizeof(int32_t));
+    off = align256b(off + (size_t)n_tmpl * (size_t)band_tab_stride(p_bands) * sizeof(int32_t));
     L.off_q = off;
-    off = align256b(off + (size_t)L.units_per_batch * (size_t)(n / 2) * cx_bytes(prec));
+    off = align256b(off + (size_t)L.units_per_batch * (size_t)band_slot_stride(n, p.n2, p_bands) * cx_bytes(prec));
     L.off_inter = off;
     off = align256b(off + (size_t)L.units_per_batch * (size_t)n * cx_bytes(prec));
     L.off_part = off;

@@ -82,9 +82,9 @@ struct FilterArgs {
     const void* raw_in;       // mf_ifft input  [units][n]
     void* raw_out;            // mf_ifft output [units][n]
     // chi^2 band mode (Eq. (5))
-    const int32_t* band_tab;  // [n_tmpl][p_bands + 2]: edges e_0..e_p, index of the transformed band
+    const int32_t* band_tab;  // [n_tmpl][2 p_bands + 3]: edges e_0..e_p, index of the transformed band, slot starts
     int32_t p_bands;
-    void* qbuf;               // [units][n/2] template x weight product, [k1][k2]
+    void* qbuf;               // [units][band_slot_stride]: the template x weight product of the bands pass 1 does not transform
     void* chi_series;         // chi^2 series output [n_series][n]
     // events: per (unit, window of 2^ev_log2w samples) u64 keys of the loudest
     // sample at or above the threshold (see event_key32 / event_key64)
