@@ -25,7 +25,7 @@
 #include "filter_tiles.hpp"
 
 #ifndef MF_BAND_WAVES
-#define MF_BAND_WAVES 4
+#define MF_BAND_WAVES 3
 #endif
 
 namespace mf {
@@ -439,10 +439,11 @@ __global__ void __launch_bounds__(NT) k_pass1_band(FilterArgs a) {
     P::run(a, smem, blockIdx.x, blockIdx.y);
 }
 
-// FP32 radix-16 rows, one row per work-group: at least 4 waves per SIMD (128
-// VGPRs).  The compiler then spills a few registers, which measured 10% faster
-// than 3 waves at 164 VGPRs.  (Shapes with several rows per work-group are
-// held below 4 waves by LDS anyway.)
+// FP32 radix-16 rows, one row per work-group: at least 3 waves per SIMD, so
+// 168 VGPRs hold the row, the accumulators and the transform without spills.
+// Measured on MI355X (2^20, p = 16, 16 units per launch): 393 us per launch,
+// against 487 us at 4 waves (128 VGPRs, where the compiler spills).  (Shapes
+// with several rows per work-group are held below 4 waves by LDS anyway.)
 template <typename T, int B, int R2>
 constexpr int band_min_waves() {
     return MF_BAND_WAVES > 0 && sizeof(T) == 4 && R2 == 16 && B == 1 ? MF_BAND_WAVES : 1;
@@ -535,11 +536,11 @@ Plan default_band_plan(int log2n, mf_precision prec) {
     MF_BAND_SHAPES(MF_BFIRST)
 #undef MF_BFIRST
     if (!found) return p;
-    // About 192 MiB of product and intermediate per batch, so that pass 2
-    // finds what pass 1 wrote still in the 256 MB last-level cache (measured at
-    // 2^20 FP32: 12 units 30.3k, 16 units 31.3k, 21 units 29.7k, 32 units 28.2k
-    // units/s).
-    const size_t bytes_per_unit = ((size_t)3 << log2n) / 2 * cx_bytes(prec);
+    // About 192 MiB of intermediates per batch (the slots add about a tenth),
+    // so that pass 2 finds what pass 1 wrote still in the 256 MB last-level
+    // cache (measured at 2^20 FP32, pass 2 per unit: 16 units 24.6 us, 21 units
+    // 24.1 us, 24 units 23.9 us, 32 units 24.0 us).
+    const size_t bytes_per_unit = ((size_t)1 << log2n) * cx_bytes(prec);
     const size_t u = ((size_t)192 << 20) / bytes_per_unit;
     p.units = (int)(u < 1 ? 1 : (u > 4096 ? 4096 : u));
     p.fused = false;

@@ -286,7 +286,7 @@ def test_set_band_plan_validation(lib):
     assert lib.mf_set_band_plan(C.byref(g), 1, None) == 0
     assert lib.mf_filter_chisq_plan(C.byref(g), 1, out) == 0
     default = list(out)
-    assert default[:6] == [256, 4096, 16, 1, 256, 256] and default[6] == 16 and default[7] == 0
+    assert default[:6] == [256, 4096, 16, 1, 256, 256] and default[6] == 24 and default[7] == 0
     w_default = int(lib.mf_filter_chisq_workspace_bytes(C.byref(g), 1, 64, 1, 16))
     r8 = (C.c_int32 * 8)(*(default[:5] + [512, 5, 0]))  # radix-8 rows, 5 units per batch
     assert lib.mf_set_band_plan(C.byref(g), 1, r8) == 0
@@ -303,7 +303,7 @@ def test_set_band_plan_validation(lib):
     bad = (C.c_int32 * 8)(512, 512, 16, 8, 512, 256, 4, 0)  # wrong N
     assert lib.mf_set_band_plan(C.byref(g), 1, bad) == -6
     # the FP64 class is separate and keeps its default
-    assert lib.mf_filter_chisq_plan(C.byref(g), 0, out) == 0 and out[6] == 8
+    assert lib.mf_filter_chisq_plan(C.byref(g), 0, out) == 0 and out[6] == 12
     assert lib.mf_set_band_plan(C.byref(g), 1, None) == 0
     assert lib.mf_filter_chisq_plan(C.byref(g), 1, out) == 0 and list(out) == default
 

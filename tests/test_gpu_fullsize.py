@@ -113,8 +113,8 @@ def _chisq_bank():
 
 
 def test_filter_chisq_fp32_default_band_plan(mf):
-    """FP32 band mode at N=2^20 with the default plan (256x4096, 16 units per batch):
-    20 templates x 2 segments (40 units, batches of 16, 16, 8).  Segment 0 holds a
+    """FP32 band mode at N=2^20 with the default plan (256x4096, 24 units per batch):
+    20 templates x 2 segments (40 units, batches of 24 and 16).  Segment 0 holds a
     matched SNR-15 1.4+1.4 injection, segment 1 a loud SNR-80 6+1.1 signal (a glitch
     for the light templates).  Every unit's peak and chi^2 at its peak; rho and
     chi^2 series of 6 units (light, heavy, injected, glitch and two uneven)."""
@@ -127,7 +127,7 @@ def test_filter_chisq_fp32_default_band_plan(mf):
     g = mf.Grid(N, FS)
     Sn, P = mf.psd(g, prefix=True)
     plan = mf.filter_chisq_plan(g, "fp32_ph64")
-    assert plan["n1"] == 256 and plan["n2"] == 4096 and plan["units_per_batch"] == 16
+    assert plan["n1"] == 256 and plan["n2"] == 4096 and plan["units_per_batch"] == 24
     bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
     st = torch.from_numpy(np.stack(segs)).to(_dev())
     series_units = [0 * 2 + 0, 1 * 2 + 0, 2 * 2 + 0, 3 * 2 + 1, 7 * 2 + 1, 15 * 2 + 0]  # u = t * n_seg + s
