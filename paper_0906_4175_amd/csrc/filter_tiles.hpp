@@ -567,6 +567,7 @@ struct Pass2 {
         const int tid = threadIdx.x;
         const int64_t u = a.unit0 + ul;
         const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
+        const __amdgpu_buffer_rsrc_t irs = buffer_rsrc(inter, (int)(N * (int64_t)sizeof(cx<T>)));
 
         if (!TAB2 && tid < B * NS) {
             const int b = tid / NS, st = tid % NS;
@@ -629,18 +630,14 @@ struct Pass2 {
                     const int j = bf % PER_ROW;
                     const int b = bf / PER_ROW;
                     if constexpr (s == 0) {
-                        // 32-bit byte offsets from the unit's base (a unit is at most
-                        // 2^22 complex values), so the loads address from a scalar base
-                        const char* ibase = (const char*)inter;
+                        // buffer loads from the unit's base (a unit is at most 2^22 complex
+                        // values): one lane offset, the distances between the inputs r in
+                        // scalar registers.  Non-temporal: each row is read once, and its
+                        // lines are not kept (measured with the non-temporal pass-1 stores)
                         const unsigned int o0 = (unsigned int)(((rb * B + b) * N2 + j) * (int)sizeof(cx<T>));
-                        // non-temporal: each row is read once, and its lines are not kept
-                        // (measured with the non-temporal pass-1 stores, below)
 #pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const vec2<T> x = __builtin_nontemporal_load(
-                                (const vec2<T>*)(ibase + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>)))));
-                            v[i][r] = cx<T>{x.x, x.y};
-                        }
+                        for (int r = 0; r < R; ++r)
+                            v[i][r] = buffer_load_cx<T, kBufferNT>(irs, o0, r * PER_ROW * (int)sizeof(cx<T>));
                         if constexpr (TAB2) {
                             // input r is k2 = j + PER_ROW r: t^{k2} = t^j (t^{PER_ROW})^r
                             // (pass 1 already applied (t^{PER_ROW})^r when a.pre0_r0 is set)

@@ -167,6 +167,7 @@ struct Pass2Band {
         const int64_t u = a.unit0 + ul;
         const int64_t t = u % a.n_tmpl;
         const cx<T>* inter = (const cx<T>*)a.inter + ul * N;
+        const __amdgpu_buffer_rsrc_t irs = buffer_rsrc(inter, (int)(N * (int64_t)sizeof(cx<T>)));
         const int P = a.p_bands;
         const int32_t* tab = a.band_tab + t * band_tab_stride(P);
         const int wb = tab[P + 1];
@@ -242,34 +243,30 @@ struct Pass2Band {
                         const int b = bf / PER_ROW;
                         [[maybe_unused]] cx<T> base = trow[b * NS + s];
                         if constexpr (s == 0) {
+                            constexpr int RB = PER_ROW * (int)sizeof(cx<T>);  // bytes between inputs r
                             if (from_inter) {
-                                // 32-bit byte offsets from the unit's base: scalar-based loads
-                                const char* ib = (const char*)inter;
                                 const unsigned int o0 = (unsigned int)(((rb * B + b) * N2 + j) * (int)sizeof(cx<T>));
 #pragma unroll
-                                for (int r = 0; r < R; ++r)
-                                    v[i][r] = *(const cx<T>*)(ib + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>))));
+                                for (int r = 0; r < R; ++r) v[i][r] = buffer_load_cx<T>(irs, o0, r * RB);
                             } else {
                                 // slot row m holds the bins s_l + m N2 + k2 (zero outside the
                                 // band): Y[k2] = sum_m slot[m N2 + k2] e^{2 pi i j1 m / N1}
-                                const char* sp = (const char*)(slots + sb);
+                                const __amdgpu_buffer_rsrc_t srs =
+                                    buffer_rsrc(slots + sb, nrow * N2 * (int)sizeof(cx<T>));
                                 const unsigned int o0 = (unsigned int)(j * (int)sizeof(cx<T>));
 #pragma unroll
-                                for (int r = 0; r < R; ++r)
-                                    v[i][r] = *(const cx<T>*)(sp + (o0 + (unsigned int)(r * PER_ROW * (int)sizeof(cx<T>))));
+                                for (int r = 0; r < R; ++r) v[i][r] = buffer_load_cx<T>(srs, o0, r * RB);
                                 for (int m = 1; m < nrow; ++m) {
                                     const cx<T> w = om[b * HALF + m];
-                                    const unsigned int om0 = o0 + (unsigned int)(m * N2 * (int)sizeof(cx<T>));
+                                    const int mo = m * N2 * (int)sizeof(cx<T>);
                                     // groups of G loads issued together, so a wave waits for the
-                                    // cache once per group (the accumulators leave few registers)
+                                    // cache once per group
                                     constexpr int G = R >= 4 ? 4 : R;
 #pragma unroll
                                     for (int r0 = 0; r0 < R; r0 += G) {
                                         cx<T> x[G];
 #pragma unroll
-                                        for (int g = 0; g < G; ++g)
-                                            x[g] = *(const cx<T>*)(sp + (om0 + (unsigned int)((r0 + g) * PER_ROW *
-                                                                                               (int)sizeof(cx<T>))));
+                                        for (int g = 0; g < G; ++g) x[g] = buffer_load_cx<T>(srs, o0, mo + (r0 + g) * RB);
 #pragma unroll
                                         for (int g = 0; g < G; ++g) {
                                             // v += x w as four fused multiply-adds

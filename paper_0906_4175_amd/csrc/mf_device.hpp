@@ -20,6 +20,29 @@ __device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
 // two-element vector of T (one 8- or 16-byte access), for the non-temporal loads and stores
 template <typename T>
 using vec2 = T __attribute__((ext_vector_type(2)));
+
+// Raw buffer loads: a base and byte range in scalar registers (a gfx9 buffer
+// descriptor with a 32-bit data format and no stride), a per-lane byte offset
+// and a wave-uniform byte offset, so unrolled loads at constant distances from
+// one lane offset need no per-load address arithmetic.  Reads outside the range
+// return zero.
+constexpr int kBufferWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufferWord3);
+}
+// AUX: the instruction's cache-policy bits (0: default, kBufferNT: non-temporal)
+constexpr int kBufferNT = 2;
+template <typename T, int AUX = 0>
+__device__ __forceinline__ cx<T> buffer_load_cx(__amdgpu_buffer_rsrc_t rs, unsigned int lane_off, int uniform_off) {
+    if constexpr (sizeof(T) == 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, uniform_off, AUX);
+        return {__uint_as_float(v[0]), __uint_as_float(v[1])};
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, uniform_off, AUX);
+        return {__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2])};
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
