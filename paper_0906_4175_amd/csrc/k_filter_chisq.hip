@@ -317,7 +317,8 @@ struct Pass2Band {
                         const int bf = tid + i * NT;
                         const int jj = bf % PER_ROW;
                         const int b = bf / PER_ROW;
-                        const unsigned int m = (sl * (unsigned int)(rb * B + b + N1 * jj)) & (unsigned int)(N - 1);
+                        // both factors < 2^24 (s_l < N/2, j < N <= 2^22): a 24-bit product suffices
+                        const unsigned int m = __umul24(sl, (unsigned int)(rb * B + b + N1 * jj)) & (unsigned int)(N - 1);
                         const cx<T> ph = root_of_unity((T)(int)m / (T)N);
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
