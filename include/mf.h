@@ -145,9 +145,12 @@ size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
  * multiplies its output by the part of the four-step factor that the first
  * row stage of pass 2 would apply (a function of the row and of the block of
  * N2/R0 columns, R0 the first row radix), so that stage has no factor (needs
- * the pass-1 columns to divide N2/R0; not with bit 0).  Bits 0-3 give bitwise the same
- * results; bit 4 moves one complex product from pass 2 to pass 1 (results
- * agree to rounding).
+ * the pass-1 columns to divide N2/R0; not with bit 0); bit 5: pass 1 runs
+ * as a persistent kernel (as many work-groups as stay resident) that takes
+ * its tiles from a queue in the workspace, the units whose templates fill
+ * the most band rows first (not with bit 0).  Bits 0-3 and 5 give bitwise the
+ * same results; bit 4 moves one complex product from pass 2 to pass 1
+ * (results agree to rounding).
  */
 mf_status mf_filter_plan(const mf_grid* grid, mf_precision prec, int32_t plan[8]);
 

@@ -18,6 +18,8 @@
 // last) whose butterflies live in registers, with LDS between stages.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "filter_tiles.hpp"
 
 namespace mf {
@@ -42,6 +44,64 @@ k_pass1(FilterArgs a) {
     using P = Pass1<T, PH, MODE, N1, N2, C, NT>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
+}
+
+// Persistent pass 1: as many work-groups as stay resident take tiles from a
+// queue (one atomic per tile) in the order k_lpt_order wrote, so the units with
+// the most band rows start first.  Every work-group leaves once the counter has
+// passed the batch's tiles.
+template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass1_min_waves<T, NT>())))
+k_pass1_lpt(FilterArgs a) {
+    using P = Pass1<T, PH, MODE, N1, N2, C, NT>;
+    __shared__ __align__(16) char smem[P::SMEM];
+    __shared__ int item;
+    constexpr int W = N2 / C;  // tiles per unit
+    const int total = (int)a.units * W;
+    for (;;) {
+        if (threadIdx.x == 0) item = (int)atomicAdd(a.lpt_ctr, 1u);
+        __syncthreads();
+        const int w = item;
+        if (w >= total) break;  // uniform over the work-group
+        P::run(a, smem, w % W, a.lpt_order[w / W]);
+        __syncthreads();  // the next tile reuses the LDS and `item`
+    }
+}
+
+// Work order of a persistent pass-1 batch, longest first: the batch's units by
+// the number of product rows their template fills (rows k1 <= k_hi / N2, in
+// kLptBuckets classes), most first, by a counting sort; the order within a
+// class is arbitrary and changes no result.  Also resets the queue counter.
+constexpr int kLptBuckets = 64;
+__global__ void __launch_bounds__(1024) k_lpt_order(const mf_bank_entry* bank, int64_t n_tmpl, int64_t unit0,
+                                                    int units, int n2, int half_rows, int32_t* order,
+                                                    unsigned int* ctr) {
+    __shared__ int pos[kLptBuckets];
+    const int tid = threadIdx.x;
+    if (tid < kLptBuckets) pos[tid] = 0;
+    __syncthreads();
+    auto bucket = [&](int i) {
+        const mf_bank_entry e = bank[(unit0 + i) % n_tmpl];  // u = s n_tmpl + t
+        const int64_t rows = e.k_hi >= e.k_lo ? e.k_hi / n2 + 1 : 0;  // <= half_rows
+        const int64_t c = rows * kLptBuckets / (half_rows + 1);
+        return (int)(c < kLptBuckets - 1 ? c : kLptBuckets - 1);
+    };
+    for (int i = tid; i < units; i += 1024) atomicAdd(&pos[bucket(i)], 1);
+    __syncthreads();
+    if (tid < 64) {
+        // exclusive prefix over the classes from the heaviest down (one wave)
+        const int c = pos[kLptBuckets - 1 - tid];
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += v;
+        }
+        pos[kLptBuckets - 1 - tid] = incl - c;
+        if (tid == 0) *ctr = 0u;
+    }
+    __syncthreads();
+    for (int i = tid; i < units; i += 1024) order[atomicAdd(&pos[bucket(i)], 1)] = i;
 }
 
 template <typename T, bool RAW, int N1, int N2, int B, int NT, int R2, int XS>
@@ -193,10 +253,13 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
         q.units = 0;                                                                                   \
         for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 ? 2 : 1); ++f) {                               \
             for (int pr = 0; pr < (pre0_fits(q) && f == 0 ? 2 : 1); ++pr) {                            \
-                q.fused = f == 1;                                                                      \
-                q.pre0 = pr == 1;                                                                      \
-                if (out && n < cap) out[n] = q;                                                        \
-                ++n;                                                                                   \
+                for (int ps = 0; ps < (f == 0 ? 2 : 1); ++ps) {                                        \
+                    q.fused = f == 1;                                                                  \
+                    q.pre0 = pr == 1;                                                                  \
+                    q.persist = ps == 1;                                                               \
+                    if (out && n < cap) out[n] = q;                                                    \
+                    ++n;                                                                               \
+                }                                                                                      \
             }                                                                                          \
         }                                                                                              \
     }
@@ -249,6 +312,13 @@ Plan default_plan(int log2n, mf_precision prec) {
     // 512 units (FP64), pass 1 unchanged; 1024 templates x 1 segment:
     // 299k-305k -> 308k-310k units/s.
     p.pre0 = pre0_fits(p);
+    // Persistent pass 1 with the heaviest units first, for the FP32 256x4096
+    // shape with 32 columns per tile.  Measured on MI355X (A/B, alternating):
+    // 32768 x 4 bank pass 1 1.529 -> 1.514 ms per 1024 units (337.8k -> 339.2k
+    // units/s), 1024 x 1 unchanged within noise (323k vs 324k); FP64 pass 1
+    // 1.51 -> 1.65 ms (its persistent form spills), so FP64 keeps one
+    // work-group per tile.
+    p.persist = prec != MF_FP64 && p.n1 == 256 && p.n2 == 4096 && p.c1 == 32;
     return p;
 }
 
@@ -275,6 +345,10 @@ FilterLayout filter_layout(const Plan& p, mf_precision prec, int64_t n, int64_t 
     L.off_tw2 = off;
     if (pass2_uses_tw2(prec, p.n2, p.b2, p.nt2))
         off = align256(off + (size_t)(kTw2Radix - 1) * kTw2Span * cx_bytes(prec));
+    // persistent pass 1: work order [units per batch] i32, then the queue counter
+    L.off_lpt = off;
+    L.off_lpt_ctr = p.persist ? align256(off + (size_t)L.units_per_batch * 4) : off;
+    if (p.persist) off = L.off_lpt_ctr + 256;
     L.total = off;
     return L;
 }
@@ -285,6 +359,29 @@ static hipError_t run_pass1(const FilterArgs& a, hipStream_t s) {
     constexpr int NT = clamp_threads(C * N1 / 16);
     dim3 grid(N2 / C, (unsigned)a.units);
     hipLaunchKernelGGL((k_pass1<T, PH, MODE, N1, N2, C, NT>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int PH, int MODE, int N1, int N2, int C>
+static hipError_t run_pass1_lpt(const FilterArgs& a, hipStream_t s) {
+    constexpr int NT = clamp_threads(C * N1 / 16);
+    auto kern = k_pass1_lpt<T, PH, MODE, N1, N2, C, NT>;
+    static std::atomic<int> per_cu{0};  // resident work-groups per CU (a property of the kernel)
+    if (per_cu.load() == 0) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, 0);
+        if (e != hipSuccess) return e;
+        per_cu.store(nb < 1 ? 1 : nb);
+    }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t tiles = a.units * (N2 / C);
+    const int64_t resident = (int64_t)per_cu.load() * cus;
+    const int64_t grid = tiles < resident ? tiles : resident;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -312,6 +409,28 @@ hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const Filter
     }
     MF_SHAPES(MF_P1)
 #undef MF_P1
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass1_lpt(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s) {
+    if (a.units <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, a.bank, a.n_tmpl, a.unit0, (int)a.units, p.n2,
+                       p.n1 / 2, (int32_t*)a.lpt_order, a.lpt_ctr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define MF_P1L(T, N1, N2, C, B, R2, XS)                                                                         \
+    if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {    \
+        if (a.pre0_r0 > 0) {                                                                                   \
+            if (std::is_same<T, float>::value && prec == MF_FP32)                                              \
+                return run_pass1_lpt<float, 1, P1_PRODUCT_PRE, N1, N2, C>(a, s);                               \
+            return run_pass1_lpt<T, 0, P1_PRODUCT_PRE, N1, N2, C>(a, s);                                       \
+        }                                                                                                      \
+        if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
+            return run_pass1_lpt<float, 1, P1_PRODUCT, N1, N2, C>(a, s);                                       \
+        return run_pass1_lpt<T, 0, P1_PRODUCT, N1, N2, C>(a, s);                                               \
+    }
+    MF_SHAPES(MF_P1L)
+#undef MF_P1L
     return hipErrorInvalidValue;
 }
 

@@ -245,15 +245,16 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     const int nt16 = clampt((long long)q.b2 * q.n2 / 16), nt8 = clampt((long long)q.b2 * q.n2 / 8);
     q.nt2 = plan[5] == nt8 ? nt8 : nt16;
     q.units = plan[6];
-    if ((plan[7] & ~31) || (plan[7] & 6) == 4)
+    if ((plan[7] & ~63) || (plan[7] & 6) == 4)
         return fail(MF_E_ARG,
                     "plan flags %d: bits 0 (pipelined step), 1 (split exchange), 2 (conflict-free layouts, with bit 1), "
-                    "3 (narrow-band pass 1), 4 (pass 1 applies the first row factor)",
+                    "3 (narrow-band pass 1), 4 (pass 1 applies the first row factor), 5 (persistent pass 1)",
                     plan[7]);
     q.fused = (plan[7] & 1) != 0;
     q.xs = (plan[7] & 4) ? 2 : ((plan[7] & 2) ? 1 : 0);
     q.prune1 = (plan[7] & 8) != 0;
     q.pre0 = (plan[7] & 16) != 0;
+    q.persist = (plan[7] & 32) != 0;
     if ((int64_t)q.n1 * q.n2 != grid->n || !mf::plan_supported(q, prec))
         return fail(MF_E_UNSUPPORTED,
                     "plan %dx%d c=%d b=%d (pass-2 threads %d, flags %d) is not built for this N/precision", q.n1, q.n2,
@@ -261,6 +262,8 @@ mf_status mf_set_plan(const mf_grid* grid, mf_precision prec, const int32_t plan
     if (q.units < 1 || q.units > 4096) return fail(MF_E_ARG, "units per batch %d outside [1, 4096]", q.units);
     if (q.pre0 && q.fused)
         return fail(MF_E_UNSUPPORTED, "flag bit 4 (pass 1 applies the first row factor) is not built for the pipelined step");
+    if (q.persist && q.fused)
+        return fail(MF_E_UNSUPPORTED, "flag bit 5 (persistent pass 1) is not built for the pipelined step");
     if (q.pre0 && !mf::pre0_fits(q))
         return fail(MF_E_UNSUPPORTED, "flag bit 4 needs the pass-1 columns (%d) to divide N2/R0 = %d", q.c1,
                     q.n2 / mf::plan_r2(q));
@@ -425,6 +428,11 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
     a.tw2 = ws + L.off_tw2;
     a.prune1 = p.prune1 ? 1 : 0;
     a.pre0_r0 = p.pre0 && !p.fused && mf::pre0_fits(p) ? mf::plan_r2(p) : 0;
+    const bool persist = p.persist && !p.fused;
+    if (persist) {
+        a.lpt_order = (const int32_t*)(ws + L.off_lpt);
+        a.lpt_ctr = (unsigned int*)(ws + L.off_lpt_ctr);
+    }
 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = mf::launch_weights(n, grid->fs, klo, prec, stilde_dev, n_seg, Sn_dev, (void*)a.wgt, s);
@@ -459,7 +467,9 @@ mf_status filter_impl(const mf_grid* grid, const void* bank_dev, int64_t n_tmpl,
             mf::FilterArgs a1 = a, none = a;
             batch(a1, b, 0);
             batch(none, -1, 0);
-            st = timed_launch(s, a1.units, none.units, [&] { return mf::launch_pass1(p, prec, false, a1, s); });
+            st = timed_launch(s, a1.units, none.units, [&] {
+                return persist ? mf::launch_pass1_lpt(p, prec, a1, s) : mf::launch_pass1(p, prec, false, a1, s);
+            });
             if (st != MF_OK) return st;
             st = timed_launch(s, none.units, a1.units, [&] { return mf::launch_pass2(p, prec, false, a1, s); });
             if (st != MF_OK) return st;

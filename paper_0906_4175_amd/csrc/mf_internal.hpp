@@ -30,10 +30,12 @@ struct Plan {
                      // after the other (half the LDS), 2 as 1 with bank-conflict-free layouts
     bool prune1;     // pass 1 skips the stage-0 transform where a band has only rows k1 < N1/16
     bool pre0;       // pass 1 applies the row factor of pass 2's first stage (see FilterArgs::pre0_r0)
+    bool persist;    // pass 1 as a persistent kernel over a queue of tiles, heaviest units first
 };
 // plan flags (last entry of the public plan array)
 inline int plan_flags(const Plan& p) {
-    return (p.fused ? 1 : 0) | (p.xs >= 1 ? 2 : 0) | (p.xs == 2 ? 4 : 0) | (p.prune1 ? 8 : 0) | (p.pre0 ? 16 : 0);
+    return (p.fused ? 1 : 0) | (p.xs >= 1 ? 2 : 0) | (p.xs == 2 ? 4 : 0) | (p.prune1 ? 8 : 0) | (p.pre0 ? 16 : 0) |
+           (p.persist ? 32 : 0);
 }
 // largest radix of the pass-2 stages (16 or 8), from the pass-2 threads
 inline int plan_r2(const Plan& p) { return p.nt2 == p.b2 * p.n2 / 8 ? 8 : 16; }
@@ -51,7 +53,7 @@ size_t cx_bytes(mf_precision prec);
 
 // Workspace carve-up of mf_filter.
 struct FilterLayout {
-    size_t off_w, off_inter, inter_bytes, off_keys, off_counts, off_part, off_tw2, total;
+    size_t off_w, off_inter, inter_bytes, off_keys, off_counts, off_part, off_tw2, off_lpt, off_lpt_ctr, total;
     int64_t units_per_batch;
 };
 // FP64 pass 2 of the 4096-point rows (three radix-16 stages, one row per
@@ -96,6 +98,11 @@ struct FilterArgs {
     // e^{2 pi i j1 floor(k2 / (N2/R0)) / (N1 R0)}, the factor pass 2's first
     // stage (radix R0 = pre0_r0) would apply to that input, and pass 2 skips it
     int32_t pre0_r0;
+    // persistent pass 1 (plan flag bit 5): the batch's units in the order their
+    // tiles are taken (most band rows first) and the queue counter, both
+    // written by k_lpt_order before each pass-1 launch
+    const int32_t* lpt_order;  // [units]
+    unsigned int* lpt_ctr;
 };
 
 // Workspace carve-up of mf_filter_chisq (band mode).
@@ -112,6 +119,8 @@ BandLayout band_layout(const Plan& p, mf_precision prec, int64_t n, int64_t n_tm
 
 // Launchers (return hipError_t of the launch)
 hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
+// persistent pass 1: the batch's work order and queue reset, then the kernel
+hipError_t launch_pass1_lpt(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s);
 hipError_t launch_pass2(const Plan& p, mf_precision prec, bool raw, const FilterArgs& a, hipStream_t s);
 hipError_t launch_step(const Plan& p, mf_precision prec, const FilterArgs& a1, const FilterArgs& a2, hipStream_t s);
 hipError_t launch_finalize(const Plan& p, mf_precision prec, const FilterArgs& a, mf_peak* peaks, hipStream_t s);

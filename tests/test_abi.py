@@ -171,13 +171,26 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert lib.mf_filter_plan(C.byref(g), 1, out) == 0
     assert list(out)[:4] == [256, 4096, 32, 1]
     # flags: bit 0 pipelined step, bit 1 split pass-2 exchange, bit 2 its conflict-free
-    # layouts, bit 3 narrow-band pass 1, bit 4 first row factor in pass 1
-    # (the 2^20 FP32 default: 2 | 4 | 8 | 16)
-    assert out[7] == 30
+    # layouts, bit 3 narrow-band pass 1, bit 4 first row factor in pass 1, bit 5
+    # persistent pass 1 (the 2^20 FP32 default: 2 | 4 | 8 | 16 | 32)
+    assert out[7] == 62
     flags = {(tuple(buf[8 * i: 8 * i + 6]), buf[8 * i + 7]) for i in range(n)}
     for f in (0, 1, 2, 3):  # separate or pipelined launches, complex or split exchange
         assert ((256, 4096, 16, 1, 256, 256), f) in flags
-    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 32)  # unknown flag bit
+    assert ((256, 4096, 16, 1, 256, 256), 32) in flags  # the tuner also times the persistent pass 1
+    for f in (32, 32 | 30):  # persistent pass 1, alone and with the default flags
+        good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, f)
+        assert lib.mf_set_plan(C.byref(g), 1, good) == 0
+        assert lib.mf_filter_plan(C.byref(g), 1, out) == 0 and out[7] == f
+    # the persistent pass 1 keeps its work order and queue counter in the workspace
+    w_lpt = int(lib.mf_filter_workspace_bytes(C.byref(g), 1, 64, 1))
+    good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 30)
+    assert lib.mf_set_plan(C.byref(g), 1, good) == 0
+    assert int(lib.mf_filter_workspace_bytes(C.byref(g), 1, 64, 1)) < w_lpt
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 32 | 1)  # with the pipelined step
+    assert lib.mf_set_plan(C.byref(g), 1, bad) == -6
+    assert b"bit 5" in lib.mf_last_error()
+    bad = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 64)  # unknown flag bit
     assert lib.mf_set_plan(C.byref(g), 1, bad) == -1
     # bit 4 (pass 1 applies the first row factor) needs the pass-1 columns to divide N2/R0
     good = (C.c_int32 * 8)(256, 4096, 16, 1, 256, 256, 16, 16 | 14)
@@ -210,8 +223,8 @@ def test_plan_candidates_and_set_plan_validation(lib):
 
 
 @pytest.mark.parametrize("n, prec, shape, threads, units, flags", [
-    (1 << 20, 1, [256, 4096, 32, 1], [512, 256], 1024, 30),   # FP32 (FP64 phase): 8 GiB of intermediates
-    (1 << 20, 2, [256, 4096, 32, 1], [512, 256], 1024, 30),   # FP32 phase: same plan class
+    (1 << 20, 1, [256, 4096, 32, 1], [512, 256], 1024, 62),   # FP32 (FP64 phase): 8 GiB of intermediates
+    (1 << 20, 2, [256, 4096, 32, 1], [512, 256], 1024, 62),   # FP32 phase: same plan class
     (1 << 20, 0, [256, 4096, 16, 1], [256, 256], 512, 26),    # FP64: padded split exchange
     (1 << 22, 1, [1024, 4096, 16, 1], [1024, 256], 256, 26),  # 4 x 2^20 samples
 ])

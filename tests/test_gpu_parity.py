@@ -338,13 +338,13 @@ def test_snr_grad_matches_oracle(mf, prec):
 # ---------------------------------------------------------------------------
 # Batching invariance: launch structure must not change results
 # ---------------------------------------------------------------------------
-def _plan(n1, n2, c, b, units, fused=False, split=False, r2=16):
+def _plan(n1, n2, c, b, units, fused=False, split=False, r2=16, persist=False):
     """A launch plan in the layout of mf_filter_plan (pass-2 threads select the row radix)."""
     def clamp(x):
         return max(64, min(1024, x))
     return {"n1": n1, "n2": n2, "cols_per_wg": c, "rows_per_wg": b, "threads_pass1": clamp(c * n1 // 16),
             "threads_pass2": clamp(b * n2 // r2), "units_per_batch": units,
-            "flags": (1 if fused else 0) | (2 if split else 0)}
+            "flags": (1 if fused else 0) | (2 if split else 0) | (32 if persist else 0)}
 
 
 @contextlib.contextmanager
@@ -400,9 +400,13 @@ def test_batching_and_fusion_bitwise_invariant(mf, prec):
     # and with the pipelined step (FP32 shape only: the FP64 shape's two passes
     # have different work-group sizes, which the step cannot mix)
     piped = run(_plan(*xs, 7, split=True, fused=prec != "fp64"))
+    # and with the persistent pass 1 (tiles from a queue, heaviest units first)
+    lpt = [run(_plan(*xs, u, split=True, persist=True)) for u in (5, 64)]
     for f in ("rho", "j", "n_above"):
         assert torch.equal(split[f], whole[f]), f
         assert torch.equal(piped[f], whole[f]), f
+        for r in lpt:
+            assert torch.equal(r[f], whole[f]), f
     if prec != "fp64":
         other = run(_plan(1024, 1024, 8, 4, 16))
         rel = (other["rho"].cpu() - ref["rho"]).abs() / ref["rho"]
