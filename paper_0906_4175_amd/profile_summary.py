@@ -46,7 +46,10 @@ def kernel_hash() -> str:
 
 
 # position of (N1, N2) among the template arguments of the transform kernels
-_SHAPE_ARGS = {"k_pass1_band": 2, "k_pass2_band": 1, "k_pass1": 3, "k_pass2": 2, "k_step": 2}
+_SHAPE_ARGS = {"k_pass1_band": 2, "k_pass2_band": 1, "k_pass1_lpt": 3, "k_pass1": 3, "k_pass2": 2, "k_step": 2}
+# the persistent pass 1 is reported under the pass-1 name of its shape (one of
+# the two forms runs in a given plan)
+_ROLE = {"k_pass1_lpt": "k_pass1"}
 
 
 def short(name: str) -> str:
@@ -54,8 +57,8 @@ def short(name: str) -> str:
         if f"::{key}<" in name:
             args = [x.strip() for x in name.split("<", 1)[1].split(">", 1)[0].split(",")]
             prec = "fp64" if args[0] == "double" else "fp32"
-            return f"{key}_{prec}_{args[at]}x{args[at + 1]}"
-    for key in ("k_pass1_band", "k_pass2_band", "k_pass1", "k_pass2", "k_step", "k_copy_probe", "k_finalize32",
+            return f"{_ROLE.get(key, key)}_{prec}_{args[at]}x{args[at + 1]}"
+    for key in ("k_pass1_band", "k_pass2_band", "k_lpt_order", "k_pass1", "k_pass2", "k_step", "k_copy_probe", "k_finalize32",
                 "k_finalize64", "k_finalize_band", "k_band_table", "k_weights", "k_sigma", "k_psd", "k_spa_synth",
                 "k_snr_grad", "k_prefix", "k_chisq", "k_events_unit", "k_events_best", "k_events_merge",
                 "k_fill_u64", "k_rfft_pack", "k_rfft_post"):
