@@ -73,6 +73,7 @@ k_pass1_lpt(FilterArgs a) {
 // kLptBuckets classes), most first, by a counting sort; the order within a
 // class is arbitrary and changes no result.  Also resets the queue counter.
 constexpr int kLptBuckets = 64;
+static_assert(kLptBuckets == 64, "the class prefix below is one wave of 64 lanes");
 __global__ void __launch_bounds__(1024) k_lpt_order(const mf_bank_entry* bank, int64_t n_tmpl, int64_t unit0,
                                                     int units, int n2, int half_rows, int32_t* order,
                                                     unsigned int* ctr) {
