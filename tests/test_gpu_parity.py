@@ -419,9 +419,22 @@ def test_batching_and_fusion_bitwise_invariant(mf, prec):
 # ---------------------------------------------------------------------------
 # HIP graph capture and the tuner
 # ---------------------------------------------------------------------------
-def test_filter_graph_capture_replays_match_eager(mf):
-    """mf_filter allocates nothing and never synchronises, so it can be captured."""
-    print("[graph]", flush=True)
+@pytest.mark.parametrize("persist", [False, True])
+def test_filter_graph_capture_replays_match_eager(mf, persist):
+    """mf_filter allocates nothing and never synchronises, so it can be captured; with the
+    persistent pass 1 (3-unit batches) each replay reorders every batch and resets its queue."""
+    print(f"[graph] persist={persist}", flush=True)
+    from paper_0906_4175_amd import tune
+    n = 1 << 16
+    plan = None
+    if persist:
+        cur = tune.current_plan(n, mf.PRECISIONS["fp32_ph64"])
+        plan = dict(cur, flags=cur["flags"] | 32, units_per_batch=3)
+    with _installed(n, "fp32_ph64", plan=plan):
+        _graph_replays_match_eager(mf)
+
+
+def _graph_replays_match_eager(mf):
     n, fs = 1 << 16, 2048.0
     s, _ = D.segment(n, fs, 321, [dict(m1=1.3, m2=1.2, snr=11.0, j0=777, phi0=0.2)])
     s2, _ = D.segment(n, fs, 322)
