@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmf.so")
-SOURCES = ["mf_api.cpp", "k_setup.hip", "k_filter.hip", "k_grad.hip", "k_chisq.hip", "k_filter_chisq.hip", "k_rfft.hip", "k_events.hip", "k_probe.hip"]
+SOURCES = ["mf_api.cpp", "k_setup.hip", "k_filter.hip", "k_pass1_lpt.hip", "k_grad.hip", "k_chisq.hip", "k_filter_chisq.hip", "k_rfft.hip", "k_events.hip", "k_probe.hip"]
 ARCH = os.environ.get("MF_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for every device compile.

@@ -18,8 +18,7 @@
 // last) whose butterflies live in registers, with LDS between stages.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
-
+#include "filter_shapes.hpp"
 #include "filter_tiles.hpp"
 
 namespace mf {
@@ -29,80 +28,12 @@ struct MaxSz {
     static constexpr size_t value = A > B ? A : B;
 };
 
-// Pass 1 keeps the occupancy its LDS allows for the wide FP32 tiles (8 waves
-// per SIMD: four 512-thread or two 1024-thread work-groups per CU, 64 VGPRs)
-// and for the FP64 256-thread tiles (4 waves, 128 VGPRs): it is bound by its
-// stores, which need many waves in flight.
-template <typename T, int NT>
-constexpr int pass1_min_waves() {
-    return sizeof(T) == 4 ? (NT >= 512 ? 8 : 1) : (NT == 256 ? 4 : 1);
-}
-
 template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass1_min_waves<T, NT>())))
 k_pass1(FilterArgs a) {
     using P = Pass1<T, PH, MODE, N1, N2, C, NT>;
     __shared__ __align__(16) char smem[P::SMEM];
     P::run(a, smem, blockIdx.x, blockIdx.y);
-}
-
-// Persistent pass 1: as many work-groups as stay resident take tiles from a
-// queue (one atomic per tile) in the order k_lpt_order wrote, so the units with
-// the most band rows start first.  Every work-group leaves once the counter has
-// passed the batch's tiles.
-template <typename T, int PH, int MODE, int N1, int N2, int C, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(pass1_min_waves<T, NT>())))
-k_pass1_lpt(FilterArgs a) {
-    using P = Pass1<T, PH, MODE, N1, N2, C, NT>;
-    __shared__ __align__(16) char smem[P::SMEM];
-    __shared__ int item;
-    constexpr int W = N2 / C;  // tiles per unit
-    const int total = (int)a.units * W;
-    for (;;) {
-        if (threadIdx.x == 0) item = (int)atomicAdd(a.lpt_ctr, 1u);
-        __syncthreads();
-        const int w = item;
-        if (w >= total) break;  // uniform over the work-group
-        P::run(a, smem, w % W, a.lpt_order[w / W]);
-        __syncthreads();  // the next tile reuses the LDS and `item`
-    }
-}
-
-// Work order of a persistent pass-1 batch, longest first: the batch's units by
-// the number of product rows their template fills (rows k1 <= k_hi / N2, in
-// kLptBuckets classes), most first, by a counting sort; the order within a
-// class is arbitrary and changes no result.  Also resets the queue counter.
-constexpr int kLptBuckets = 64;
-static_assert(kLptBuckets == 64, "the class prefix below is one wave of 64 lanes");
-__global__ void __launch_bounds__(1024) k_lpt_order(const mf_bank_entry* bank, int64_t n_tmpl, int64_t unit0,
-                                                    int units, int n2, int half_rows, int32_t* order,
-                                                    unsigned int* ctr) {
-    __shared__ int pos[kLptBuckets];
-    const int tid = threadIdx.x;
-    if (tid < kLptBuckets) pos[tid] = 0;
-    __syncthreads();
-    auto bucket = [&](int i) {
-        const mf_bank_entry e = bank[(unit0 + i) % n_tmpl];  // u = s n_tmpl + t
-        const int64_t rows = e.k_hi >= e.k_lo ? e.k_hi / n2 + 1 : 0;  // <= half_rows
-        const int64_t c = rows * kLptBuckets / (half_rows + 1);
-        return (int)(c < kLptBuckets - 1 ? c : kLptBuckets - 1);
-    };
-    for (int i = tid; i < units; i += 1024) atomicAdd(&pos[bucket(i)], 1);
-    __syncthreads();
-    if (tid < 64) {
-        // exclusive prefix over the classes from the heaviest down (one wave)
-        const int c = pos[kLptBuckets - 1 - tid];
-        int incl = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o, 64);
-            if (tid >= o) incl += v;
-        }
-        pos[kLptBuckets - 1 - tid] = incl - c;
-        if (tid == 0) *ctr = 0u;
-    }
-    __syncthreads();
-    for (int i = tid; i < units; i += 1024) order[atomicAdd(&pos[bucket(i)], 1)] = i;
 }
 
 template <typename T, bool RAW, int N1, int N2, int B, int NT, int R2, int XS>
@@ -201,37 +132,7 @@ __global__ void __launch_bounds__(64) k_finalize64(const Partial64* part, int n_
 // ---------------------------------------------------------------------------
 size_t cx_bytes(mf_precision prec) { return prec == MF_FP64 ? 16 : 8; }
 
-static constexpr int clamp_threads(int x) { return x < 64 ? 64 : (x > 1024 ? 1024 : x); }
 
-// Every (precision, N1, N2, C, B, R2, XS) instantiated (R2: largest radix of
-// the pass-2 stages, 16 or 8; it sets the pass-2 threads B N2 / R2.  XS: 1 the
-// pass-2 stages exchange real and imaginary parts separately, in half the
-// LDS; 2 the same with bank-conflict-free layouts).  The first entry for each
-// N and precision is its default plan.
-#define MF_SHAPES(X)                                                                                              \
-    X(float, 32, 32, 16, 32, 16, 0) X(float, 32, 64, 16, 32, 16, 0) X(float, 64, 64, 16, 64, 16, 0)                 \
-    X(float, 64, 128, 16, 32, 16, 0) X(float, 128, 128, 16, 32, 16, 0) X(float, 128, 256, 16, 16, 16, 0)            \
-    X(float, 256, 256, 16, 16, 16, 0) X(float, 256, 512, 16, 8, 16, 0) X(float, 512, 512, 16, 8, 16, 0)             \
-    X(float, 512, 1024, 16, 4, 16, 0) X(float, 256, 4096, 32, 1, 16, 2) X(float, 256, 4096, 16, 1, 16, 1)           \
-    X(float, 256, 4096, 16, 1, 16, 0)                                                                              \
-    X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 16, 1, 16, 1) X(float, 1024, 4096, 16, 1, 16, 0)        \
-    X(float, 1024, 4096, 8, 1, 16, 0) X(float, 1024, 4096, 8, 1, 16, 1)                                           \
-    X(float, 1024, 1024, 8, 4, 16, 0) X(float, 1024, 1024, 16, 8, 16, 0) X(float, 1024, 1024, 16, 4, 16, 0)         \
-    X(float, 512, 2048, 16, 2, 16, 0) X(float, 2048, 512, 8, 8, 16, 0) X(float, 2048, 2048, 8, 2, 16, 0)            \
-    X(float, 512, 8192, 16, 1, 16, 0) X(float, 256, 4096, 16, 1, 8, 0)                                             \
-    X(float, 1024, 4096, 8, 1, 8, 0) X(float, 256, 4096, 32, 1, 16, 1) X(float, 256, 4096, 16, 1, 16, 2)          \
-    X(float, 1024, 4096, 16, 1, 16, 2)                                                                            \
-    X(double, 32, 32, 8, 32, 16, 0) X(double, 32, 64, 8, 32, 16, 0) X(double, 64, 64, 8, 64, 16, 0)                 \
-    X(double, 64, 128, 8, 32, 16, 0) X(double, 128, 128, 8, 32, 16, 0) X(double, 128, 256, 8, 16, 16, 0)            \
-    X(double, 256, 256, 8, 16, 16, 0) X(double, 256, 512, 8, 8, 16, 0) X(double, 512, 512, 8, 8, 16, 0)             \
-    X(double, 512, 1024, 8, 4, 16, 0) X(double, 256, 4096, 16, 1, 16, 1) X(double, 256, 4096, 8, 1, 16, 1)         \
-    X(double, 512, 2048, 8, 2, 16, 0)                                                                              \
-    X(double, 1024, 2048, 4, 2, 16, 0)                                                                             \
-    X(double, 2048, 2048, 2, 2, 16, 0) X(double, 1024, 1024, 8, 4, 16, 0) X(double, 1024, 1024, 4, 4, 16, 0)        \
-    X(double, 1024, 1024, 4, 2, 16, 0) X(double, 512, 2048, 8, 2, 8, 0) X(double, 256, 4096, 8, 1, 16, 0)         \
-    X(double, 256, 4096, 16, 1, 16, 2)
-
-static bool want(mf_precision prec, bool f64) { return (prec == MF_FP64) == f64; }
 
 static void fill(Plan& p, int n1, int n2, int c1, int b2, int r2, int xs) {
     p.n1 = n1;
@@ -363,29 +264,6 @@ static hipError_t run_pass1(const FilterArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int PH, int MODE, int N1, int N2, int C>
-static hipError_t run_pass1_lpt(const FilterArgs& a, hipStream_t s) {
-    constexpr int NT = clamp_threads(C * N1 / 16);
-    auto kern = k_pass1_lpt<T, PH, MODE, N1, N2, C, NT>;
-    static std::atomic<int> per_cu{0};  // resident work-groups per CU (a property of the kernel)
-    if (per_cu.load() == 0) {
-        int nb = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, 0);
-        if (e != hipSuccess) return e;
-        per_cu.store(nb < 1 ? 1 : nb);
-    }
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    const int64_t tiles = a.units * (N2 / C);
-    const int64_t resident = (int64_t)per_cu.load() * cus;
-    const int64_t grid = tiles < resident ? tiles : resident;
-    if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, a);
-    return hipGetLastError();
-}
-
 template <typename T, bool RAW, int N1, int N2, int B, int R2, int XS>
 static hipError_t run_pass2(const FilterArgs& a, hipStream_t s) {
     static_assert(N1 % B == 0 && B <= N1, "pass-2 rows per work-group must tile N1");
@@ -410,28 +288,6 @@ hipError_t launch_pass1(const Plan& p, mf_precision prec, bool raw, const Filter
     }
     MF_SHAPES(MF_P1)
 #undef MF_P1
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_pass1_lpt(const Plan& p, mf_precision prec, const FilterArgs& a, hipStream_t s) {
-    if (a.units <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, a.bank, a.n_tmpl, a.unit0, (int)a.units, p.n2,
-                       p.n1 / 2, (int32_t*)a.lpt_order, a.lpt_ctr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-#define MF_P1L(T, N1, N2, C, B, R2, XS)                                                                         \
-    if (want(prec, std::is_same<T, double>::value) && p.n1 == N1 && p.n2 == N2 && p.c1 == C && p.b2 == B) {    \
-        if (a.pre0_r0 > 0) {                                                                                   \
-            if (std::is_same<T, float>::value && prec == MF_FP32)                                              \
-                return run_pass1_lpt<float, 1, P1_PRODUCT_PRE, N1, N2, C>(a, s);                               \
-            return run_pass1_lpt<T, 0, P1_PRODUCT_PRE, N1, N2, C>(a, s);                                       \
-        }                                                                                                      \
-        if (std::is_same<T, float>::value && prec == MF_FP32)                                                  \
-            return run_pass1_lpt<float, 1, P1_PRODUCT, N1, N2, C>(a, s);                                       \
-        return run_pass1_lpt<T, 0, P1_PRODUCT, N1, N2, C>(a, s);                                               \
-    }
-    MF_SHAPES(MF_P1L)
-#undef MF_P1L
     return hipErrorInvalidValue;
 }
 
