@@ -29,13 +29,13 @@ constexpr int pass1_min_waves() {
     X(float, 256, 256, 16, 16, 16, 0) X(float, 256, 512, 16, 8, 16, 0) X(float, 512, 512, 16, 8, 16, 0)             \
     X(float, 512, 1024, 16, 4, 16, 0) X(float, 256, 4096, 32, 1, 16, 2) X(float, 256, 4096, 16, 1, 16, 1)           \
     X(float, 256, 4096, 16, 1, 16, 0)                                                                              \
-    X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 16, 1, 16, 1) X(float, 1024, 4096, 16, 1, 16, 0)        \
+    X(float, 1024, 2048, 16, 2, 16, 0) X(float, 1024, 4096, 16, 1, 16, 2) X(float, 1024, 4096, 16, 1, 16, 1)        \
+    X(float, 1024, 4096, 16, 1, 16, 0)                                                                             \
     X(float, 1024, 4096, 8, 1, 16, 0) X(float, 1024, 4096, 8, 1, 16, 1)                                           \
     X(float, 1024, 1024, 8, 4, 16, 0) X(float, 1024, 1024, 16, 8, 16, 0) X(float, 1024, 1024, 16, 4, 16, 0)         \
     X(float, 512, 2048, 16, 2, 16, 0) X(float, 2048, 512, 8, 8, 16, 0) X(float, 2048, 2048, 8, 2, 16, 0)            \
     X(float, 512, 8192, 16, 1, 16, 0) X(float, 256, 4096, 16, 1, 8, 0)                                             \
     X(float, 1024, 4096, 8, 1, 8, 0) X(float, 256, 4096, 32, 1, 16, 1) X(float, 256, 4096, 16, 1, 16, 2)          \
-    X(float, 1024, 4096, 16, 1, 16, 2)                                                                            \
     X(double, 32, 32, 8, 32, 16, 0) X(double, 32, 64, 8, 32, 16, 0) X(double, 64, 64, 8, 64, 16, 0)                 \
     X(double, 64, 128, 8, 32, 16, 0) X(double, 128, 128, 8, 32, 16, 0) X(double, 128, 256, 8, 16, 16, 0)            \
     X(double, 256, 256, 8, 16, 16, 0) X(double, 256, 512, 8, 8, 16, 0) X(double, 512, 512, 8, 8, 16, 0)             \

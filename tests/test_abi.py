@@ -219,14 +219,14 @@ def test_plan_candidates_and_set_plan_validation(lib):
     assert lib.mf_set_plan(C.byref(g), 1, None) == 0
     g22 = _grid(n=1 << 22)
     assert lib.mf_filter_plan(C.byref(g22), 1, out) == 0
-    assert list(out)[:4] == [1024, 4096, 16, 1] and out[7] == 26
+    assert list(out)[:4] == [1024, 4096, 16, 1] and out[7] == 30
 
 
 @pytest.mark.parametrize("n, prec, shape, threads, units, flags", [
     (1 << 20, 1, [256, 4096, 32, 1], [512, 256], 1024, 62),   # FP32 (FP64 phase): 8 GiB of intermediates
     (1 << 20, 2, [256, 4096, 32, 1], [512, 256], 1024, 62),   # FP32 phase: same plan class
     (1 << 20, 0, [256, 4096, 16, 1], [256, 256], 512, 26),    # FP64: padded split exchange
-    (1 << 22, 1, [1024, 4096, 16, 1], [1024, 256], 256, 26),  # 4 x 2^20 samples
+    (1 << 22, 1, [1024, 4096, 16, 1], [1024, 256], 256, 30),  # 4 x 2^20 samples: conflict-free exchange
 ])
 def test_default_plans(lib, n, prec, shape, threads, units, flags):
     g = _grid(n=n)
