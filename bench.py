@@ -580,7 +580,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the launch plan on the workload first")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
               "the per-GPU share of a sharded bank is the single-GPU workload.", file=sys.stderr)
         sys.exit(2)
     wl = synth.WORKLOADS[args.workload]

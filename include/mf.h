@@ -53,7 +53,7 @@ typedef enum {
     MF_E_BAND = -3,        /* empty band (k_hi < k_lo) or f_low out of range */
     MF_E_HIP = -4,         /* HIP runtime error                             */
     MF_E_WORKSPACE = -5,   /* workspace too small                           */
-    MF_E_UNSUPPORTED = -6  /* valid request this build does not implement   */
+    MF_E_UNSUPPORTED = -6  /* valid request the library does not implement  */
 } mf_status;
 
 typedef enum {
