@@ -1,8 +1,10 @@
 """Launch-plan autotuner for mf_filter.
 
 The library builds a fixed list of transform shapes (N1 x N2 split, columns
-per pass-1 work-group, rows per pass-2 work-group) and can run pass 1 of one
-batch together with pass 2 of the previous one in a single launch.  `tune`
+per pass-1 work-group, rows per pass-2 work-group) and, per shape, launch
+structures (the flags of mf_filter_plan): pass 1 of one batch together with
+pass 2 of the previous one in a single launch, a persistent pass 1 with a
+longest-first queue, the first row factor applied in pass 1.  `tune`
 times every built shape, each launch structure and a set of batch sizes on
 the caller's real workload with HIP events on the current stream, installs the
 fastest with mf_set_plan and can record it in a JSON cache keyed by
