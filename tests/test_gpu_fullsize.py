@@ -6,6 +6,7 @@
 * The batched uneven bank (8192 templates x 8 segments) with the default
   batching: 256 seeded units.
 * rho^2 and its gradient (adjoint kernel) for triggers with t_c up to 255 s.
+* The chi^2 band mode at N = 2^22 (1024 s at 4096 Hz) with its default plan.
 
 Bars (readings of "rho rel err <= 1e-4" and of the peak tie rule):
   series   max_j |rho_g - rho_o| / max(rho_o, 1) <= 1e-4
@@ -310,3 +311,41 @@ def test_refinement_full_size_matches_oracle_driven_twin(mf, monkeypatch):
     ratio = F_o.numpy() / np.array(F_inj)
     print("  final F / F(injection):", np.round(ratio, 4), flush=True)
     assert np.median(ratio) > 0.995
+
+
+def test_filter_chisq_fp32_four_million_points(mf):
+    """FP32 band mode at N = 2^22 with its default plan (2048 x 2048 rows of 2048
+    bins, so the band slots are rows of 2048): a 1.4+1.4 injection of SNR 15 and a
+    10+1.5 template, rho and chi^2 series of both against the oracle."""
+    print("[chisq 2^22] setup", flush=True)
+    n, p = 1 << 22, 16
+    s, Sn_ref = D.segment(n, FS, synth.seed_sequence(41).spawn(1)[0],
+                          [dict(m1=1.4, m2=1.4, snr=15.0, j0=2500003, phi0=0.7)])
+    mc, eta = synth.mc_eta([1.4, 10.0], [1.4, 1.5])
+    g = mf.Grid(n, FS)
+    Sn, P = mf.psd(g, prefix=True)
+    plan = mf.filter_chisq_plan(g, "fp32_ph64")
+    assert plan["n1"] == 2048 and plan["n2"] == 2048
+    bank = mf.spa_bank(g, mc, eta, Sn, "fp32_ph64")
+    st = torch.from_numpy(s[None]).to(_dev())
+    res = mf.filter_chisq(g, bank, st, Sn, P, "fp32_ph64", p_bands=p, series_units=[0, 1])
+    rho, j, chi = (res[k].cpu().numpy() for k in ("rho", "j", "chisq"))
+    rs, cs = res["series"].cpu().numpy(), res["chisq_series"].cpu().numpy()
+    s64 = s.astype(np.complex128)
+    for t in range(2):
+        print(f"[chisq 2^22] oracle unit {t}", flush=True)
+        h = O.spa_template(n, FS, 40.0, float(mc[t]), float(eta[t]))
+        k_lo, k_hi = O.band(n, FS, 40.0, float(mc[t]), float(eta[t]))
+        sig = math.sqrt(O.sigma_sq(h, Sn_ref, FS / n))
+        chi_ref, zl = O.chisq_series(s64, Sn_ref, h, n, FS, k_lo, k_hi, p)
+        rho_ref = np.abs(zl.sum(0)) / sig
+        del zl
+        assert D.series_error(rs[t].astype(np.float64), rho_ref) <= 1e-4, t
+        scale = chi_ref + rho_ref ** 2 + 1.0
+        assert float(np.max(np.abs(cs[t].astype(np.float64) - chi_ref) / scale)) <= 1e-4, t
+        jo = int(np.argmax(rho_ref))
+        assert D.peak_index_ok(int(j[t, 0]), rho_ref, jo), t
+        assert abs(float(rho[t, 0]) - rho_ref[jo]) <= 1e-4 * rho_ref[jo], t
+        assert abs(float(chi[t, 0]) - chi_ref[int(j[t, 0])]) <= 1e-4 * scale[int(j[t, 0])], t
+    assert abs(int(j[0, 0]) - 2500003) <= 2 and float(rho[0, 0]) > 12.0  # the injection, within noise
+    assert chi[0, 0] < 2.5 * (2 * p - 2)
