@@ -127,7 +127,9 @@ size_t mf_bank_bytes(int64_t n_tmpl);
  * arguments, with mf_last_error set).  The bulk is one batch of
  * intermediates, min(n_tmpl * n_seg, units per batch) * N complex values: the
  * default plans batch about 8 GiB (1024 units at N = 2^20 in the FP32 modes),
- * so a large bank needs about 8 GiB plus N/2+1 complex weights per segment. */
+ * so a large bank needs about 8 GiB plus N/2+1 complex weights per segment
+ * (plus, with the persistent pass 1 of plan flag bit 5, one int32 work-order
+ * entry per unit of a batch and a queue counter). */
 size_t mf_filter_workspace_bytes(const mf_grid* grid, mf_precision prec,
                                  int64_t n_tmpl, int64_t n_seg);
 
