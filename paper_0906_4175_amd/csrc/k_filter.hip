@@ -153,6 +153,7 @@ int plan_candidates(int log2n, mf_precision prec, Plan* out, int cap) {
         Plan q{};                                                                                      \
         fill(q, N1, N2, C, B, R2, XS);                                                                 \
         q.units = 0;                                                                                   \
+        q.prune1 = true; /* bitwise the same results, never slower */                                  \
         for (int f = 0; f < (q.nt1 == q.nt2 && R2 == 16 ? 2 : 1); ++f) {                               \
             for (int pr = 0; pr < (pre0_fits(q) && f == 0 ? 2 : 1); ++pr) {                            \
                 for (int ps = 0; ps < (f == 0 ? 2 : 1); ++ps) {                                        \
